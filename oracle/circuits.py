@@ -1,0 +1,177 @@
+"""Gate and SQL circuits of the oracle (test infrastructure only).
+
+The FHE-SQL server (Algorithm 2, Section 4.3) builds a boolean mask per row by
+evaluating the WHERE expression homomorphically and then selects
+If-Then-Else(mask, value, enc(0)) (Eqs. 2-3), optionally summing the selected
+values (the aggregation equations that follow them).  With TFHE gate
+bootstrapping these become boolean circuits over bit-wise encrypted integers
+(least significant bit first).  The gates are the TFHE paper's bootstrapped
+gates (ePrint 2018/421, Sec. 4.2): a linear combination of the input
+ciphertexts plus a constant, followed by a sign bootstrap that outputs
++-1/8.  A bit b is the torus value (2b - 1)/8.
+
+Circuits are written once over a ``backend`` so the same netlist runs on
+plaintext booleans (to pin its logic exhaustively) and on ciphertexts
+(``CipherBackend``, built on the C oracle).
+
+Readings of points the paper leaves open (each listed in the design doc):
+* equality: XNOR per bit, then a balanced AND tree pairing (0,1), (2,3), ...,
+  an odd element passing up unchanged;
+* a < c: borrow chain b_j = MAJ(not a_j, c_j, b_{j-1}), b_{-1} = FALSE;
+* a > c is c < a; BETWEEN lo AND hi is NOR(a < lo, hi < a);
+* select: AND(mask, v_j) per bit (If-Then-Else with an encrypted zero);
+* SUM: pairwise adder tree in row order, ripple-carry adders whose carry-out
+  becomes the new top bit; an odd operand is zero-extended by one FALSE bit.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import (gate_bootstrap, lincomb, parallel_map, qmask)
+
+# op -> (constant in units of 1/8, input weights)
+GATES = {
+    "AND": (-1, (1, 1)),
+    "NAND": (1, (-1, -1)),
+    "OR": (1, (1, 1)),
+    "NOR": (-1, (-1, -1)),
+    "XOR": (2, (2, 2)),
+    "XNOR": (-2, (-2, -2)),
+    "ANDNY": (-1, (-1, 1)),   # (not x) and y
+    "MAJ": (0, (1, 1, 1)),
+}
+
+
+class PlainBackend:
+    """Boolean reference semantics of each gate."""
+    TRUE, FALSE = True, False
+
+    def gate(self, op, *xs):
+        x = [bool(v) for v in xs]
+        if op == "AND": return x[0] and x[1]
+        if op == "NAND": return not (x[0] and x[1])
+        if op == "OR": return x[0] or x[1]
+        if op == "NOR": return not (x[0] or x[1])
+        if op == "XOR": return x[0] != x[1]
+        if op == "XNOR": return x[0] == x[1]
+        if op == "ANDNY": return (not x[0]) and x[1]
+        if op == "MAJ": return (x[0] + x[1] + x[2]) >= 2
+        raise ValueError(op)
+
+    def neg(self, x):
+        return not x
+
+
+class CipherBackend:
+    """Bootstrapped gates on LWE ciphertexts (uint64 arrays of n+1 words)."""
+
+    def __init__(self, p, keys):
+        self.p = p
+        self.keys = keys
+        eighth = 1 << (p.q - 3)
+        self.TRUE = np.zeros(p.n + 1, dtype=np.uint64)
+        self.TRUE[p.n] = eighth
+        self.FALSE = np.zeros(p.n + 1, dtype=np.uint64)
+        self.FALSE[p.n] = (-eighth) & qmask(p.q)
+        self.count = 0
+
+    def combine(self, op, *xs):
+        c8, w = GATES[op]
+        const = (c8 * (1 << (self.p.q - 3))) & qmask(self.p.q)
+        return lincomb(self.p, np.stack(xs), w, const)
+
+    def gate(self, op, *xs):
+        self.count += 1
+        return gate_bootstrap(self.p, self.keys.bsk, self.keys.ksk, self.combine(op, *xs))
+
+    def neg(self, x):
+        out = (np.uint64(0) - np.asarray(x, dtype=np.uint64))
+        return out & np.uint64(qmask(self.p.q))
+
+
+def eq(be, a, c):
+    xs = [be.gate("XNOR", a[j], c[j]) for j in range(len(a))]
+    while len(xs) > 1:
+        nxt = [be.gate("AND", xs[2 * i], xs[2 * i + 1]) for i in range(len(xs) // 2)]
+        if len(xs) % 2:
+            nxt.append(xs[-1])
+        xs = nxt
+    return xs[0]
+
+
+def lt(be, a, c):
+    b = be.gate("MAJ", be.neg(a[0]), c[0], be.FALSE)
+    for j in range(1, len(a)):
+        b = be.gate("MAJ", be.neg(a[j]), c[j], b)
+    return b
+
+
+def gt(be, a, c):
+    return lt(be, c, a)
+
+
+def between(be, a, lo, hi):
+    return be.gate("NOR", lt(be, a, lo), lt(be, hi, a))
+
+
+def predicate(be, op, a, lit_a, lit_b=None):
+    if op == "eq": return eq(be, a, lit_a)
+    if op == "lt": return lt(be, a, lit_a)
+    if op == "gt": return gt(be, a, lit_a)
+    if op == "between": return between(be, a, lit_a, lit_b)
+    raise ValueError(op)
+
+
+def select(be, m, v):
+    return [be.gate("AND", m, v[j]) for j in range(len(v))]
+
+
+def add(be, x, y):
+    """Ripple-carry sum of two equal-width operands; width grows by one."""
+    s = [be.gate("XOR", x[0], y[0])]
+    c = be.gate("AND", x[0], y[0])
+    for j in range(1, len(x)):
+        t = be.gate("XOR", x[j], y[j])
+        s.append(be.gate("XOR", t, c))
+        c = be.gate("MAJ", x[j], y[j], c)
+    s.append(c)
+    return s
+
+
+def sum_tree(be, operands):
+    """Pairwise adder tree over rows (0,1), (2,3), ...; odd leftover is
+    zero-extended by one FALSE bit so every operand of a level has one width."""
+    level = [list(o) for o in operands]
+    while len(level) > 1:
+        nxt = [add(be, level[2 * i], level[2 * i + 1]) for i in range(len(level) // 2)]
+        if len(level) % 2:
+            nxt.append(level[-1] + [be.FALSE])
+        level = nxt
+    return level[0]
+
+
+# ------------------------------------------------------------------ drivers
+
+def mask_rows(p, keys, op, col_cts, lit_a, lit_b=None, threads=None):
+    """Oracle WHERE mask for every row: col_cts [rows][w][n+1] -> [rows][n+1]."""
+    def one(r):
+        be = CipherBackend(p, keys)
+        return predicate(be, op, list(col_cts[r]), list(lit_a),
+                         list(lit_b) if lit_b is not None else None)
+    return np.stack(parallel_map(one, range(len(col_cts)), threads))
+
+
+def select_rows(p, keys, masks, col_cts, threads=None):
+    """Oracle masked select: AND(mask_r, bit) -> [rows][w][n+1]."""
+    def one(r):
+        be = CipherBackend(p, keys)
+        return np.stack(select(be, masks[r], list(col_cts[r])))
+    return np.stack(parallel_map(one, range(len(col_cts)), threads))
+
+
+def gate_batch(p, keys, op, ins, threads=None):
+    """One bootstrapped gate per row of ins ([B][nin][n+1])."""
+    def one(i):
+        be = CipherBackend(p, keys)
+        return be.gate(op, *ins[i])
+    return np.stack(parallel_map(one, range(len(ins)), threads))
