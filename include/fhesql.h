@@ -1,0 +1,188 @@
+/*
+ * fhesql.h -- C ABI of the MI355X (gfx950) TFHE oblivious-selection library.
+ *
+ * What it computes.  The FHE-SQL paper's server loop (Algorithm 2, Section 4)
+ * evaluates the WHERE expression of a query homomorphically for every row,
+ * producing one encrypted boolean per row (the selection mask M_enc,
+ * Section 4.3), and then applies If-Then-Else(mask, value, enc(0)) to the
+ * selected columns (Eqs. 2-3 of Section 6.D), optionally summing the
+ * selected values (the aggregation equations after Eq. 3).  Its
+ * homomorphic operations are TFHE's (the paper's Section 2.2 cites the TFHE
+ * paper, ePrint 2018/421, and uses its boolean gates).  This library
+ * implements that server path on one GPU with TFHE gate bootstrapping:
+ *   bootstrap = blind rotation (gadget decomposition + GGSW x GLWE external
+ *   products) -> sample extraction -> LWE key switching,
+ * and boolean circuits of bootstrapped gates for =, <, >, BETWEEN, the
+ * masked select and the masked SUM.
+ *
+ * Conventions (all calls).
+ *  - Torus values are uint32_t words when torus_bits = 32 and uint64_t words
+ *    when torus_bits = 64 ("words" below).  Arithmetic is mod 2^torus_bits.
+ *  - LWE ciphertext of dimension d: d mask words then the body (d+1 words).
+ *    "small" LWE: d = n (under the LWE key s); "big" LWE: d = k*N (under the
+ *    extracted GLWE key).  A batch of B ciphertexts is B*(d+1) contiguous words.
+ *  - Bits are encoded as (2b-1)/8 on the torus; integers are given bit-wise,
+ *    least significant bit first: a column of `rows` w-bit values is
+ *    rows*w*(n+1) words, bit j of row r at ((r*w)+j)*(n+1).
+ *  - Pointers named d_* are device pointers (HIP global memory) owned by the
+ *    caller; they must stay valid until the stream has finished the call.
+ *    Outputs must not alias inputs.  h_* pointers are host memory.
+ *  - Calls are asynchronous on the given HIP stream (NULL = default stream)
+ *    and are not thread-safe for one context.  Results are a pure function of
+ *    the keys and inputs: batching and scheduling never change an output bit.
+ *  - Return value: 0 on success, else a negative error code (below);
+ *    tfhe_last_error() gives a message.  No C++ exception crosses the ABI.
+ */
+#ifndef FHESQL_H
+#define FHESQL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TFHE_OK 0
+#define TFHE_EINVAL (-1)   /* bad argument or parameter set */
+#define TFHE_ESHAPE (-2)   /* size or shape mismatch */
+#define TFHE_ENOMEM (-3)   /* device workspace allocation failed */
+#define TFHE_EHIP (-4)     /* HIP runtime error (including an earlier async fault) */
+
+/* TFHE parameters.  k must be 1; N a power of two in [64, 2048];
+ * 1 <= l, l*bg_bits <= torus_bits; ks_t*ks_base_bits <= torus_bits. */
+typedef struct tfhe_params {
+    uint32_t torus_bits;   /* 32 or 64 */
+    uint32_t n;            /* LWE dimension */
+    uint32_t k;            /* GLWE dimension */
+    uint32_t N;            /* GLWE polynomial size */
+    uint32_t bg_bits;      /* log2 of the gadget base Bg */
+    uint32_t l;            /* gadget levels */
+    uint32_t ks_base_bits; /* log2 of the key-switching base */
+    uint32_t ks_t;         /* key-switching levels */
+} tfhe_params;
+
+typedef struct tfhe_ctx tfhe_ctx;
+
+/* Blind-rotation kernel selection: the exact limb-split int8 MFMA external
+ * product (default) or the plain scalar-integer one.  Both give identical bits. */
+#define TFHE_KERNEL_MFMA 0
+#define TFHE_KERNEL_PLAIN 1
+
+/* SQL comparison operators (operators are plaintext metadata, Section 4.3 B). */
+#define SQL_OP_EQ 0
+#define SQL_OP_LT 1
+#define SQL_OP_GT 2
+#define SQL_OP_BETWEEN 3
+
+/* Sizes in words of the key material for a parameter set:
+ * BSK [n][(k+1)l][k+1][N] (GGSW encryptions of the LWE key bits) and
+ * KSK [kN][ks_t][2^ks_base_bits][n+1] (LWE encryptions of v*s'_i/B^j).
+ * Returns 0 for invalid parameters. */
+size_t tfhe_bsk_words(const tfhe_params* p);
+size_t tfhe_ksk_words(const tfhe_params* p);
+
+/* Create a context: validates p, copies the keys to the device (bsk/ksk are
+ * host pointers if keys_on_device == 0, device pointers otherwise; sizes in
+ * bytes must match tfhe_bsk_words/tfhe_ksk_words), builds the device-only
+ * limb-planar Toeplitz form of the BSK and allocates workspace lazily.
+ * The context owns its copies; the caller keeps ownership of bsk/ksk. */
+int tfhe_ctx_create(const tfhe_params* p, const void* bsk, size_t bsk_bytes,
+                    const void* ksk, size_t ksk_bytes, int keys_on_device,
+                    tfhe_ctx** out);
+void tfhe_ctx_destroy(tfhe_ctx* ctx);
+const char* tfhe_last_error(const tfhe_ctx* ctx);
+/* Select TFHE_KERNEL_MFMA or TFHE_KERNEL_PLAIN for later blind rotations. */
+int tfhe_set_kernel(tfhe_ctx* ctx, int kind);
+/* Waits for the stream and reports any asynchronous fault. */
+int tfhe_ctx_sync(tfhe_ctx* ctx, void* hip_stream);
+
+/* Blind rotation + sample extraction (TFHE bootstrapping without the key
+ * switch) of B small LWE ciphertexts d_lwe_in [B][n+1].  d_testv: N words of
+ * the test polynomial, or NULL for the gate test polynomial (all 1/8).
+ * d_out [B][kN+1]: big LWE ciphertexts under the extracted key. */
+int tfhe_bootstrap_batch(tfhe_ctx* ctx, const void* d_lwe_in, const void* d_testv,
+                         void* d_out, uint32_t B, void* hip_stream);
+
+/* LWE key switching of B big ciphertexts d_in [B][kN+1] to d_out [B][n+1]. */
+int tfhe_keyswitch_batch(tfhe_ctx* ctx, const void* d_in, void* d_out, uint32_t B,
+                         void* hip_stream);
+
+/* Bootstrapped boolean gates on B independent input tuples: d_x, d_y (and
+ * d_z for MAJ) [B][n+1]; d_out [B][n+1].  op: 0 AND, 1 NAND, 2 OR, 3 NOR,
+ * 4 XOR, 5 XNOR, 6 ANDNY (not x and y), 7 MAJ. */
+int tfhe_gate_batch(tfhe_ctx* ctx, int op, const void* d_x, const void* d_y,
+                    const void* d_z, void* d_out, uint32_t B, void* hip_stream);
+
+/* WHERE mask of a column scan (Algorithm 2's mask loop; Eq. 1 for equality):
+ * d_mask[r] = enc(col[r] op lit) for every row.  d_col [rows][w][n+1];
+ * d_lit_a [w][n+1] (encrypted literal bits); d_lit_b: upper literal for
+ * BETWEEN (lit_a <= col <= lit_b), else NULL; d_mask [rows][n+1]. */
+int sql_mask_scan(tfhe_ctx* ctx, const void* d_col, uint32_t rows, uint32_t w, int op,
+                  const void* d_lit_a, const void* d_lit_b, void* d_mask, void* hip_stream);
+
+/* Masked select (If-Then-Else with an encrypted zero, Eqs. 2-3):
+ * d_out[r][j] = AND(mask[r], col[r][j]).  d_out [rows][w][n+1]. */
+int sql_masked_select(tfhe_ctx* ctx, const void* d_mask, const void* d_col, uint32_t rows,
+                      uint32_t w, void* d_out, void* hip_stream);
+
+/* Masked SUM (the aggregation of the selected entries): d_sum receives the
+ * encrypted bits of sum_r mask[r]*col[r], width w + ceil(log2 rows),
+ * [width][n+1].  *width_out returns that width. */
+int sql_masked_sum(tfhe_ctx* ctx, const void* d_mask, const void* d_col, uint32_t rows,
+                   uint32_t w, void* d_sum, uint32_t* width_out, void* hip_stream);
+
+/* One table scan of a batch: mask (and optionally the masked select). */
+typedef struct sql_table_query {
+    const void* d_col;     /* [rows][w][n+1] predicate column */
+    const void* d_sel_col; /* [rows][w][n+1] selected column or NULL (mask only) */
+    uint32_t rows;
+    uint32_t w;
+    int op;
+    const void* d_lit_a;   /* [w][n+1] */
+    const void* d_lit_b;   /* [w][n+1] for BETWEEN else NULL */
+    void* d_mask;          /* [rows][n+1] */
+    void* d_sel_out;       /* [rows][w][n+1] or NULL */
+} sql_table_query;
+
+/* Many tables with uneven row counts and mixed predicates in one level-batched
+ * schedule: every level's gates of all tables go into one launch sequence.
+ * use_graph != 0 captures the whole schedule into one HIP graph and launches
+ * it once. */
+int sql_scan_batch(tfhe_ctx* ctx, const sql_table_query* q, uint32_t count, int use_graph,
+                   void* hip_stream);
+
+/* ---- client-side helpers on the device (synthetic data and checks) ---- */
+
+/* Counter-based SplitMix64 stream: value i of (seed, tag) is
+ * mix64(K + (i+1)*0x9E3779B97F4A7C15), K = mix64(seed ^ mix64(tag + 0x9E3779B97F4A7C15)).
+ * Fills d_out[count] (uint64_t) with values start .. start+count-1. */
+int tfhe_rng_fill(uint64_t seed, uint64_t tag, uint64_t start, uint64_t count, void* d_out,
+                  void* hip_stream);
+
+/* Key generation on the device from seeded streams (the tags of the seeded
+ * input recipe): binary keys s (n words) and S (kN words) written to
+ * d_lwe_key / d_glwe_key (words holding 0/1), BSK and KSK to d_bsk / d_ksk
+ * (tfhe_bsk_words / tfhe_ksk_words words).  sigma_log2 values give the
+ * noise standard deviations 2^-lwe_sigma_log2 and 2^-glwe_sigma_log2. */
+int tfhe_keygen(const tfhe_params* p, uint64_t seed, uint32_t lwe_sigma_log2,
+                uint32_t glwe_sigma_log2, void* d_lwe_key, void* d_glwe_key, void* d_bsk,
+                void* d_ksk, void* hip_stream);
+
+/* Encrypt `count` plaintext torus values d_mu[count] (words) under the LWE
+ * key d_key (n words of 0/1) with seeded masks/noise: ciphertext i uses mask
+ * values (start+i)*n .. and noise sample start+i of the (seed, tag) streams.
+ * d_out [count][n+1]. */
+int tfhe_lwe_encrypt(const tfhe_params* p, uint64_t seed, uint64_t mask_tag,
+                     uint64_t noise_tag, uint32_t sigma_log2, uint64_t start,
+                     const void* d_key, const void* d_mu, void* d_out, uint64_t count,
+                     uint32_t dim, void* hip_stream);
+
+/* Phases b - <a, s> of count LWE ciphertexts of dimension dim: d_out[count] words. */
+int tfhe_lwe_phase(const tfhe_params* p, const void* d_key, const void* d_cts, void* d_out,
+                   uint64_t count, uint32_t dim, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FHESQL_H */

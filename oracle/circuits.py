@@ -175,3 +175,75 @@ def gate_batch(p, keys, op, ins, threads=None):
         be = CipherBackend(p, keys)
         return be.gate(op, *ins[i])
     return np.stack(parallel_map(one, range(len(ins)), threads))
+
+
+# ------------------------------------------------- level-parallel evaluation
+
+class _Node:
+    __slots__ = ("op", "ins", "depth", "val")
+
+    def __init__(self, op, ins, depth):
+        self.op, self.ins, self.depth, self.val = op, ins, depth, None
+
+
+class _Neg:
+    __slots__ = ("x", "depth")
+
+    def __init__(self, x, depth):
+        self.x, self.depth = x, depth
+
+
+class LazyBackend:
+    """Records the netlist of a circuit instead of evaluating it, so that all
+    gates of one depth (over many rows) can be bootstrapped in parallel.
+    Leaves are ciphertext arrays; constants are the trivial ciphertexts."""
+
+    def __init__(self, p):
+        self.p = p
+        eighth = 1 << (p.q - 3)
+        self.TRUE = np.zeros(p.n + 1, dtype=np.uint64)
+        self.TRUE[p.n] = eighth
+        self.FALSE = np.zeros(p.n + 1, dtype=np.uint64)
+        self.FALSE[p.n] = (-eighth) & qmask(p.q)
+        self.nodes = []
+
+    @staticmethod
+    def _depth(x):
+        return x.depth if isinstance(x, (_Node, _Neg)) else 0
+
+    def gate(self, op, *xs):
+        nd = _Node(op, xs, 1 + max(self._depth(x) for x in xs))
+        self.nodes.append(nd)
+        return nd
+
+    def neg(self, x):
+        return _Neg(x, self._depth(x))
+
+
+def _value(p, x):
+    if isinstance(x, _Node):
+        return x.val
+    if isinstance(x, _Neg):
+        return (np.uint64(0) - _value(p, x.x)) & np.uint64(qmask(p.q))
+    return np.asarray(x, dtype=np.uint64)
+
+
+def evaluate(p, keys, lazy: LazyBackend, threads=None):
+    """Bootstrap every recorded gate, depth by depth, on a thread pool."""
+    by_depth = {}
+    for nd in lazy.nodes:
+        by_depth.setdefault(nd.depth, []).append(nd)
+    cb = CipherBackend(p, keys)
+
+    def run(nd):
+        nd.val = cb.gate(nd.op, *[_value(p, x) for x in nd.ins])
+
+    for d in sorted(by_depth):
+        parallel_map(run, by_depth[d], threads)
+
+
+def resolve(p, x):
+    """Value of a recorded node (after evaluate) or of a leaf."""
+    if isinstance(x, list):
+        return np.stack([resolve(p, v) for v in x])
+    return _value(p, x)

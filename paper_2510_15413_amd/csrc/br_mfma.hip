@@ -1,0 +1,382 @@
+// Blind rotation + sample extraction with an exact limb-split int8 MFMA
+// external product (gfx950, v_mfma_i32_16x16x64_i8).
+//
+// TFHE bootstrapping (ePrint 2018/421, Alg. 3 / Sec. 4): for i = 0..n-1,
+//   ACC <- ACC + ExtProd(BSK_i, X^{abar_i} ACC - ACC),
+// ExtProd(G, C)_v = sum_{u,p} Dec_p(C_u) * G[u*l+p-1][v] (negacyclic products).
+//
+// Mapping.  For one step and one (u, p, v), all ciphertexts of a batch share
+// the key polynomial K = G[u*l+p-1][v], so the products of the batch are one
+// matrix product Out[N x B] = T(K)[N x N] . D[N x B] with the negacyclic
+// Toeplitz matrix T(K)[j][kk] = Kext[j - kk] (Kext[t] = K[t] for t >= 0 and
+// -K[t+N] for t < 0) and D the digit matrix of the batch.  K is split into
+// balanced int8 limbs, K = sum_m 2^{8m} K_m (mod 2^q); each limb product is
+// exact in int32 (|limb| <= 128, |digit| <= Bg/2, N terms) and the sum
+// sum_m 2^{8m} P_m is formed mod 2^q, so the result is bit-exact.
+//
+// Workgroup = 16 ciphertexts (the MFMA N dimension) for all n steps, 8 waves.
+// Wave w owns output component v = w/4 and the row tiles J = (w%4) + 4a of
+// 16 consecutive coefficients.  K chunks are 64 coefficients.  The A operand
+// of tile (J, c) depends only on the diagonal c - a (Toeplitz), so one A
+// fragment is loaded per diagonal and reused by every (a, c) on it.
+// The key limbs of step i are stored (once per context) as reversed extended
+// byte arrays S[x] = limb(Kext[N-1-x]); a lane's 16 A bytes are contiguous
+// in S (unaligned by a per-lane constant, fixed with v_alignbyte).
+// Accumulators live in a per-workgroup global ping-pong buffer laid out
+// [v][N/4][16 cts][4 coefs] (L2/MALL resident); digits and key limbs in LDS.
+#include "fhesql_internal.h"
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+constexpr int CTS = 16;
+constexpr int THREADS = 512;
+
+struct BrArgs {
+    const void* lwe;          // [B][n+1] words
+    const int8_t* bsk8;       // [n][2l][2][LIMBS][2N]
+    const void* tv;           // test polynomials [ntv][N] words
+    const int32_t* tv_index;  // [B] or null
+    void* out;                // [B][N+1] words
+    void* ws;                 // [grid][2][2N*16] words
+    int B, n, l, bg_bits;
+};
+
+template <typename T>
+FHE_DEV size_t acc_idx(int N, int v, int j, int c) {
+    return ((size_t)(v * (N >> 2) + (j >> 2)) * CTS + c) * 4 + (j & 3);
+}
+
+// Gadget digits of the rotate-diff X^{abar} ACC_u - ACC_u for 16 cts, written
+// in the MFMA B-fragment layout: block (u*l+p, chunk) of 1 KB, lane (g,c) holds
+// the 16 digits of coefficients 64*chunk + 16*g + 0..15 of ciphertext c.
+template <typename T, int R>
+FHE_DEV void digits_phase(const T* __restrict__ src, const uint16_t* abar, int n, int i,
+                          int8_t* dbuf, int u_lo, int u_cnt, int p_only, int l, int bgb) {
+    constexpr int N = R * 64;
+    constexpr int Q = Torus<T>::Q;
+    const int lb = l * bgb;
+    const uint32_t bgm = (1u << bgb) - 1;
+    const int half = 1 << (bgb - 1);
+    uint32_t off = 0;
+    for (int p = 0; p < l; p++) off += (uint32_t)half << (p * bgb);
+    const int items = CTS * u_cnt * (N / 4);
+    for (int it = threadIdx.x; it < items; it += THREADS) {
+        const int c = it & (CTS - 1);
+        const int rest = it >> 4;
+        const int kg = rest & (N / 4 - 1);
+        const int u = u_lo + rest / (N / 4);
+        const int ab = abar[c * n + i];
+        const T* P = src + (size_t)u * (N / 4) * CTS * 4;
+        auto at = [&](int x) -> T { return P[((size_t)(x >> 2) * CTS + c) * 4 + (x & 3)]; };
+        uint32_t y[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int j = 4 * kg + e;
+            T rot = monomial_coef<T>(at, N, ab, j);
+            T Y = (T)(rot - at(j));
+            y[e] = (uint32_t)round_top<T>(Y, lb) + off;
+        }
+        (void)Q;
+        const int j0 = 4 * kg;
+        const int ch = j0 >> 6, g = (j0 >> 4) & 3, bo = j0 & 15;
+        for (int p = 0; p < l; p++) {
+            if (p_only >= 0 && p != p_only) continue;
+            const int sh = (l - 1 - p) * bgb;
+            uint32_t packed = 0;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                int d = (int)((y[e] >> sh) & bgm) - half;
+                packed |= ((uint32_t)(d & 0xFF)) << (8 * e);
+            }
+            const int blk = p_only >= 0 ? 0 : (u * l + p);
+            *(uint32_t*)(dbuf + ((size_t)blk * R + ch) * 1024 + (g * 16 + c) * 16 + bo) = packed;
+        }
+    }
+}
+
+struct ARaw {
+    uint32_t w[5];
+};
+
+// The 5 dwords covering a lane's 16 A bytes S[b .. b+15] (b unaligned).
+FHE_DEV ARaw afrag_raw(const uint8_t* S, int b) {
+    const uint32_t* w = (const uint32_t*)(S + (b & ~3));
+    ARaw r;
+#pragma unroll
+    for (int k = 0; k < 5; k++) r.w[k] = w[k];
+    return r;
+}
+
+FHE_DEV v4i afrag_combine(const ARaw& r, int sh) {
+    v4i a;
+    a[0] = (int)__builtin_amdgcn_alignbyte(r.w[1], r.w[0], sh);
+    a[1] = (int)__builtin_amdgcn_alignbyte(r.w[2], r.w[1], sh);
+    a[2] = (int)__builtin_amdgcn_alignbyte(r.w[3], r.w[2], sh);
+    a[3] = (int)__builtin_amdgcn_alignbyte(r.w[4], r.w[3], sh);
+    return a;
+}
+
+// One (u,p) key block for this wave: all limbs, the pass's RP row tiles.
+template <typename T, int R, int RP>
+FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr, int pass,
+                        T (&delta)[RP][4]) {
+    constexpr int N = R * 64;
+    constexpr int NL = Torus<T>::LIMBS;
+    constexpr int CP = R < 16 ? R : 16;
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int lanebase = (N - 1) - 16 * jr - r + 16 * g;
+    const int sh = lanebase & 3;
+    for (int cg = 0; cg < R / CP; cg++) {
+        v4i bf[CP];
+#pragma unroll
+        for (int cc = 0; cc < CP; cc++)
+            bf[cc] = *(const v4i*)(dblk + (size_t)(cg * CP + cc) * 1024 + lane * 16);
+#pragma unroll 1
+        for (int m = 0; m < NL; m++) {
+            const uint8_t* S = kslot + (size_t)(v * NL + m) * (2 * N);
+            v4i acc[RP];
+#pragma unroll
+            for (int a = 0; a < RP; a++) acc[a] = v4i{0, 0, 0, 0};
+            // diagonals d = c - a (local); the raw LDS loads of diagonal d+1 are
+            // issued before the MFMAs of diagonal d and combined after them
+            const int dg0 = -(RP - 1) + cg * CP - pass * RP;
+            v4i A = afrag_combine(afrag_raw(S, lanebase + 64 * dg0), sh);
+#pragma unroll
+            for (int d = -(RP - 1); d <= CP - 1; d++) {
+                ARaw nxt;
+                if (d < CP - 1) nxt = afrag_raw(S, lanebase + 64 * (d + 1 + cg * CP - pass * RP));
+#pragma unroll
+                for (int a = 0; a < RP; a++) {
+                    const int cl = a + d;
+                    if (cl >= 0 && cl < CP)
+                        acc[a] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, bf[cl], acc[a], 0, 0, 0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                if (d < CP - 1) A = afrag_combine(nxt, sh);
+            }
+#pragma unroll
+            for (int a = 0; a < RP; a++)
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+                    delta[a][e] += (T)((T)(int64_t)acc[a][e] << (8 * m));
+        }
+    }
+}
+
+template <typename T, int R, int RP, bool DALL>
+__global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void br_mfma_kernel(BrArgs a) {
+    constexpr int N = R * 64;
+    constexpr int NL = Torus<T>::LIMBS;
+    constexpr int KSLOT = 2 * NL * 2 * N;  // bytes of one (u,p) key block
+    constexpr int KV = (KSLOT / 16 + THREADS - 1) / THREADS;
+    constexpr int LG = __builtin_ctz(2 * N);
+    constexpr bool DOUBLE = DALL;
+    const int n = a.n, l = a.l, NB = 2 * l;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ct0 = blockIdx.x * CTS;
+    const T* lwe = (const T*)a.lwe;
+
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    uint16_t* abar = (uint16_t*)smem;
+    size_t off = ((size_t)CTS * n * 2 + 15) & ~(size_t)15;
+    int8_t* dbuf = (int8_t*)(smem + off);
+    off += (size_t)(DALL ? NB : 1) * R * 1024;
+    uint8_t* kbuf = smem + off;
+
+    T* ws0 = (T*)a.ws + (size_t)blockIdx.x * 2 * (2 * N * CTS);
+    T* ws1 = ws0 + 2 * N * CTS;
+
+    // ---- prologue: modulus switch, accumulator = (0, X^{-bbar} testv)
+    for (int idx = tid; idx < CTS * n; idx += THREADS) {
+        const int c = idx / n, i = idx - c * n;
+        const int gi = ct0 + c;
+        abar[idx] = gi < a.B ? (uint16_t)mod_switch<T>(lwe[(size_t)gi * (n + 1) + i], LG) : 0;
+    }
+    for (int idx = tid; idx < CTS * N; idx += THREADS) {
+        const int c = idx & (CTS - 1), j = idx >> 4;
+        const int gi = ct0 + c;
+        T body = 0;
+        if (gi < a.B) {
+            const int bb = (int)mod_switch<T>(lwe[(size_t)gi * (n + 1) + n], LG);
+            const int e = (2 * N - bb) & (2 * N - 1);
+            const T* tv = (const T*)a.tv + (size_t)(a.tv_index ? a.tv_index[gi] : 0) * N;
+            body = monomial_coef<T>([&](int s) -> T { return tv[s]; }, N, e, j);
+        }
+        ws0[acc_idx<T>(N, 0, j, c)] = 0;
+        ws0[acc_idx<T>(N, 1, j, c)] = body;
+    }
+
+    const int v = wave >> 2, jr = wave & 3;
+    constexpr int NPASS = R / RP;
+    constexpr int KU = KSLOT / 16;  // uint4 per key block
+    uint4 pre[KV];
+#define KEY_LOAD(SRCPTR)                                                   \
+    do {                                                                   \
+        const uint4* ks_ = (SRCPTR);                                       \
+        _Pragma("unroll") for (int q_ = 0; q_ < KV; q_++) {                \
+            const int idx_ = tid + q_ * THREADS;                           \
+            pre[q_] = (KU % THREADS == 0 || idx_ < KU) ? ks_[idx_ < KU ? idx_ : 0] : make_uint4(0, 0, 0, 0); \
+        }                                                                  \
+    } while (0)
+#define KEY_STORE(DSTPTR)                                                  \
+    do {                                                                   \
+        uint4* kd_ = (uint4*)(DSTPTR);                                     \
+        _Pragma("unroll") for (int q_ = 0; q_ < KV; q_++) {                \
+            const int idx_ = tid + q_ * THREADS;                           \
+            if (KU % THREADS == 0 || idx_ < KU) kd_[idx_] = pre[q_];       \
+        }                                                                  \
+    } while (0)
+    const uint4* kbase = (const uint4*)a.bsk8;
+    if (DOUBLE) {
+        KEY_LOAD(kbase);
+        KEY_STORE(kbuf);
+    }
+    __syncthreads();
+
+    T* src = ws0;
+    T* dst = ws1;
+    int t = 0;  // linear key-block counter over (i, pass, ub)
+    for (int i = 0; i < n; i++) {
+        if (DALL) {
+            digits_phase<T, R>(src, abar, n, i, dbuf, 0, 2, -1, l, a.bg_bits);
+            __syncthreads();
+        }
+        for (int pass = 0; pass < NPASS; pass++) {
+            T delta[RP][4];
+#pragma unroll
+            for (int q = 0; q < RP; q++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) delta[q][e] = 0;
+            for (int ub = 0; ub < NB; ub++, t++) {
+                if (!DALL) digits_phase<T, R>(src, abar, n, i, dbuf, ub / l, 1, ub % l, l, a.bg_bits);
+                if (DOUBLE) {
+                    // prefetch the next block of the (i, pass, ub) sequence
+                    int ni = i, nub = ub + 1, npass = pass;
+                    if (nub == NB) { nub = 0; npass++; if (npass == NPASS) { npass = 0; ni++; } }
+                    if (ni < n) KEY_LOAD(kbase + ((size_t)ni * NB + nub) * KU);
+                } else {
+                    KEY_LOAD(kbase + ((size_t)i * NB + ub) * KU);
+                    KEY_STORE(kbuf);
+                }
+                __syncthreads();
+                const uint8_t* kslot = kbuf + (DOUBLE ? (size_t)(t & 1) * KSLOT : 0);
+                const int8_t* dblk = dbuf + (DALL ? (size_t)ub * R * 1024 : 0);
+                mfma_block<T, R, RP>(kslot, dblk, v, jr, pass, delta);
+                if (DOUBLE) KEY_STORE(kbuf + (size_t)((t + 1) & 1) * KSLOT);
+                __syncthreads();
+            }
+            // dst rows of this pass = src rows + delta (16-byte accesses; all
+            // loads issued before the stores).  Row tile J = jr + 4a holds
+            // coefficients 16J + 4(lane>>4) + e of ciphertext lane&15.
+            {
+                typedef T vec4 __attribute__((ext_vector_type(4)));
+                const size_t base0 = acc_idx<T>(N, v, 16 * (jr + 4 * pass * RP) + 4 * (lane >> 4), lane & 15);
+                constexpr size_t STEP = (size_t)(64 / 4) * CTS * 4;  // 4 row tiles further
+                vec4 cur[RP];
+#pragma unroll
+                for (int q = 0; q < RP; q++) cur[q] = *(const vec4*)(src + base0 + q * STEP);
+#pragma unroll
+                for (int q = 0; q < RP; q++) {
+                    vec4 o;
+#pragma unroll
+                    for (int e = 0; e < 4; e++) o[e] = (T)(cur[q][e] + delta[q][e]);
+                    *(vec4*)(dst + base0 + q * STEP) = o;
+                }
+            }
+        }
+        __syncthreads();
+        T* tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+
+#undef KEY_LOAD
+#undef KEY_STORE
+    // ---- sample extraction: a'_0 = A[0], a'_j = -A[N-j], b' = B[0]
+    T* out = (T*)a.out;
+    for (int idx = tid; idx < CTS * (N + 1); idx += THREADS) {
+        const int c = idx / (N + 1), j = idx - c * (N + 1);
+        const int gi = ct0 + c;
+        if (gi >= a.B) continue;
+        T val;
+        if (j == 0) val = src[acc_idx<T>(N, 0, 0, c)];
+        else if (j < N) val = (T)(0 - src[acc_idx<T>(N, 0, N - j, c)]);
+        else val = src[acc_idx<T>(N, 1, 0, c)];
+        out[(size_t)gi * (N + 1) + j] = val;
+    }
+}
+
+template <typename T, int R, int RP, bool DALL>
+int launch_t(tfhe_ctx* c, const BrArgs& a, size_t lds, hipStream_t s) {
+    auto k = br_mfma_kernel<T, R, RP, DALL>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return hip_check(c, e, "hipFuncSetAttribute(br_mfma)");
+    const unsigned grid = (a.B + CTS - 1) / CTS;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(THREADS), lds, s, a);
+    return hip_check(c, hipGetLastError(), "launch br_mfma");
+}
+
+size_t lds_need(const tfhe_ctx* c, bool dall) {
+    const int N = c->p.N, l = c->p.l;
+    const int NL = c->q == 32 ? 4 : 8;
+    const size_t kslot = 2ull * NL * 2 * N;
+    size_t b = (((size_t)CTS * c->p.n * 2) + 15) & ~(size_t)15;
+    b += (size_t)(dall ? 2 * l : 1) * (N / 64) * 1024;
+    b += (dall ? 2 : 1) * kslot;
+    return b;
+}
+
+template <typename T, int R, int RP>
+int dispatch_dall(tfhe_ctx* c, const BrArgs& a, hipStream_t s) {
+    const size_t max_lds = (size_t)c->prop.maxSharedMemoryPerMultiProcessor > 0
+                               ? (size_t)c->prop.maxSharedMemoryPerMultiProcessor
+                               : (size_t)160 * 1024;
+    size_t need = lds_need(c, true);
+    if (need <= max_lds) return launch_t<T, R, RP, true>(c, a, need, s);
+    need = lds_need(c, false);
+    if (need > max_lds) return ctx_fail(c, TFHE_EINVAL, "parameters exceed LDS capacity of the MFMA kernel");
+    return launch_t<T, R, RP, false>(c, a, need, s);
+}
+
+}  // namespace
+
+size_t mfma_ws_bytes(const tfhe_ctx* c, uint32_t B) {
+    const size_t grid = (B + CTS - 1) / CTS;
+    return grid * 2 * 2 * (size_t)c->p.N * CTS * word_bytes(c);
+}
+
+int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_t* tv_index,
+                   void* big_out, uint32_t B, void* ws, hipStream_t s) {
+    BrArgs a;
+    a.lwe = lwe_in;
+    a.bsk8 = c->d_bsk8;
+    a.tv = tv;
+    a.tv_index = tv_index;
+    a.out = big_out;
+    a.ws = ws;
+    a.B = (int)B;
+    a.n = (int)c->p.n;
+    a.l = (int)c->p.l;
+    a.bg_bits = (int)c->p.bg_bits;
+    const int N = (int)c->p.N;
+    if (c->q == 32) {
+        switch (N) {
+            case 64: return dispatch_dall<uint32_t, 1, 1>(c, a, s);
+            case 256: return dispatch_dall<uint32_t, 4, 4>(c, a, s);
+            case 512: return dispatch_dall<uint32_t, 8, 8>(c, a, s);
+            case 1024: return dispatch_dall<uint32_t, 16, 16>(c, a, s);
+            case 2048: return dispatch_dall<uint32_t, 32, 8>(c, a, s);
+        }
+    } else {
+        switch (N) {
+            case 64: return dispatch_dall<uint64_t, 1, 1>(c, a, s);
+            case 256: return dispatch_dall<uint64_t, 4, 4>(c, a, s);
+            case 512: return dispatch_dall<uint64_t, 8, 4>(c, a, s);
+            case 1024: return dispatch_dall<uint64_t, 16, 4>(c, a, s);
+            case 2048: return dispatch_dall<uint64_t, 32, 4>(c, a, s);
+        }
+    }
+    return ctx_fail(c, TFHE_EINVAL, "unsupported N for the MFMA kernel");
+}

@@ -1,0 +1,161 @@
+// Internal definitions of the gfx950 TFHE library: context, device helpers
+// and kernel launchers shared by the translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/fhesql.h"
+
+#define FHE_DEV __device__ __forceinline__
+
+// ------------------------------------------------------------------ torus
+
+template <typename T> struct Torus;
+template <> struct Torus<uint32_t> {
+    static constexpr int Q = 32;
+    static constexpr int LIMBS = 4;  // balanced int8 limbs of a key word
+};
+template <> struct Torus<uint64_t> {
+    static constexpr int Q = 64;
+    static constexpr int LIMBS = 8;
+};
+
+// Round x to its top `bits` bits, ties up: floor((x + 2^(Q-bits-1)) / 2^(Q-bits)).
+template <typename T>
+FHE_DEV T round_top(T x, int bits) {
+    constexpr int Q = Torus<T>::Q;
+    if (bits >= Q) return x;
+    const int sh = Q - bits;
+    return (T)((x + ((T)1 << (sh - 1))) >> sh);
+}
+
+// Modulus switch to Z_2N (log2(2N) = lg2n bits).
+template <typename T>
+FHE_DEV uint32_t mod_switch(T x, int lg2n) { return (uint32_t)round_top<T>(x, lg2n); }
+
+// Coefficient j of X^e * P (e in [0, 2N)) read through an accessor p(idx).
+template <typename T, typename F>
+FHE_DEV T monomial_coef(F p, int N, int e, int j) {
+    int neg = e >= N;
+    int es = neg ? e - N : e;
+    int s = j - es;
+    T v = s >= 0 ? p(s) : (T)(0 - p(s + N));
+    return neg ? (T)(0 - v) : v;
+}
+
+// ------------------------------------------------------- SplitMix64 stream
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__host__ __device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint64_t tag) {
+    return mix64(seed ^ mix64(tag + kGamma));
+}
+// Value `idx` of the stream with key K.
+__host__ __device__ __forceinline__ uint64_t stream_at(uint64_t K, uint64_t idx) {
+    return mix64(K + (idx + 1) * kGamma);
+}
+// Uniform q-bit torus value (top bits).
+template <typename T>
+__host__ __device__ __forceinline__ T stream_torus(uint64_t K, uint64_t idx) {
+    uint64_t v = stream_at(K, idx);
+    return Torus<T>::Q == 64 ? (T)v : (T)(v >> 32);
+}
+// Centred Irwin-Hall error (12 uniform 32-bit halves of values 6s..6s+5),
+// scaled to std 2^(Q - sigma_log2), ties rounded up.
+template <typename T>
+__host__ __device__ __forceinline__ T stream_noise(uint64_t K, uint64_t s, int sigma_log2) {
+    int64_t acc = -((int64_t)6 << 32);
+    for (int t = 0; t < 6; t++) {
+        uint64_t v = stream_at(K, 6 * s + t);
+        acc += (int64_t)(v >> 32) + (int64_t)(v & 0xFFFFFFFFull);
+    }
+    const int shift = 32 - Torus<T>::Q + sigma_log2;
+    int64_t e = shift > 0 ? ((acc + ((int64_t)1 << (shift - 1))) >> shift) : (int64_t)((uint64_t)acc << (-shift));
+    return (T)(uint64_t)e;
+}
+
+// ------------------------------------------------------------------ gates
+
+// Bootstrapped gates (TFHE gate bootstrapping): constant in units of 1/8 and
+// input weights of the linear combination that precedes the sign bootstrap.
+enum GateOp { G_AND = 0, G_NAND, G_OR, G_NOR, G_XOR, G_XNOR, G_ANDNY, G_MAJ, G_LUT };
+
+struct GateForm {
+    int c8;
+    int nin;
+    int w[3];
+};
+inline GateForm gate_form(int op) {
+    switch (op) {
+        case G_AND: return {-1, 2, {1, 1, 0}};
+        case G_NAND: return {1, 2, {-1, -1, 0}};
+        case G_OR: return {1, 2, {1, 1, 0}};
+        case G_NOR: return {-1, 2, {-1, -1, 0}};
+        case G_XOR: return {2, 2, {2, 2, 0}};
+        case G_XNOR: return {-2, 2, {-2, -2, 0}};
+        case G_ANDNY: return {-1, 2, {-1, 1, 0}};
+        case G_MAJ: return {0, 3, {1, 1, 1}};
+        default: return {0, 0, {0, 0, 0}};
+    }
+}
+
+// One strided group of gates of a level: gate r (0 <= r < rows) combines
+// in[j] + r*in_stride[j] (word addresses) with weights w[j] and a constant,
+// and writes its bootstrapped output to out + r*out_stride.  Constant
+// (trivial) operands are folded into `cst` by the host, so the nin inputs
+// are real ciphertexts.
+struct Segment {
+    uint64_t in[3];
+    int64_t in_stride[3];
+    uint64_t out;
+    int64_t out_stride;
+    uint64_t cst;     // constant body term (torus word)
+    int32_t w[3];
+    int32_t nin;
+    uint32_t rows;
+    int32_t lut;      // test polynomial index, -1 = gate test polynomial
+};
+
+// ---------------------------------------------------------------- context
+
+struct tfhe_ctx {
+    tfhe_params p{};
+    int q = 32;
+    int kernel = TFHE_KERNEL_MFMA;
+    void* d_bsk = nullptr;     // [n][(k+1)l][k+1][N] words
+    int8_t* d_bsk8 = nullptr;  // [n][(k+1)l][k+1][LIMBS][2N] Toeplitz limb form
+    void* d_ksk = nullptr;     // [kN][t][2^b][n+1] words
+    void* d_gate_tv = nullptr; // N words of 1/8
+    void* d_false = nullptr;   // trivial FALSE ciphertext (0^n, -1/8)
+    // workspace pool (grown on demand)
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    std::string err;
+    hipDeviceProp_t prop{};
+};
+
+int ctx_fail(tfhe_ctx* c, int code, const std::string& msg);
+int hip_check(tfhe_ctx* c, hipError_t e, const char* what);
+int ctx_reserve(tfhe_ctx* c, size_t bytes);
+
+size_t word_bytes(const tfhe_ctx* c);
+
+// kernel launchers (each returns a TFHE_* code)
+int launch_bsk_limbs(tfhe_ctx* c, hipStream_t s);
+int launch_blind_rotate(tfhe_ctx* c, const void* lwe_in, const void* testv_table,
+                        const int32_t* tv_index, void* big_out, uint32_t B, void* ws,
+                        hipStream_t s);
+size_t blind_rotate_ws_bytes(const tfhe_ctx* c, uint32_t B);
+int launch_keyswitch(tfhe_ctx* c, const void* big_in, void* out, const uint64_t* out_ptrs,
+                     uint32_t B, hipStream_t s);
+int launch_combine(tfhe_ctx* c, const Segment* d_segs, const uint32_t* d_seg_start,
+                   int nseg, uint32_t total, void* lwe_out, uint64_t* out_ptrs,
+                   int32_t* tv_index, hipStream_t s);

@@ -1,0 +1,509 @@
+// Gate circuits of the FHE-SQL server path on the GPU.
+//
+// Algorithm 2 of the paper computes a mask bit per row by evaluating the
+// WHERE expression tree homomorphically, then If-Then-Else(mask, value,
+// enc(0)) on the selected columns (Eqs. 2-3), optionally summing the selected
+// values.  With TFHE gate bootstrapping each operation is a boolean circuit
+// over bit-wise encrypted integers (LSB first):
+//   equality  : XNOR per bit, balanced AND tree (pairs (0,1),(2,3),...; an
+//               odd element passes up);
+//   a < c     : borrow chain b_j = MAJ(not a_j, c_j, b_{j-1}), b_{-1} = FALSE;
+//   a > c     : c < a;   BETWEEN lo AND hi: NOR(a < lo, hi < a);
+//   select    : AND(mask, v_j) per bit;
+//   SUM       : pairwise ripple-carry adder tree over rows in row order, the
+//               carry-out as new top bit, an odd operand zero-extended.
+// A netlist is a list of levels; a level is a list of strided segments
+// (one gate per row of a group).  Each level runs as three kernels over the
+// gates of every segment: linear combination, blind rotation + sample
+// extraction (MFMA or plain), key switching into the gate outputs.
+#include <algorithm>
+#include <cstring>
+
+#include "fhesql_internal.h"
+
+// ------------------------------------------------------------- combine
+
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void combine_kernel(const Segment* __restrict__ segs, const uint32_t* __restrict__ start,
+                                                      int nseg, uint32_t total, T* out, uint64_t* out_ptrs,
+                                                      int32_t* tv_index, int n) {
+    const uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= total) return;
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {  // last segment with start <= g
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    const Segment& sg = segs[lo];
+    const int64_t r = (int64_t)(g - start[lo]);
+    const T* in0 = (const T*)(uintptr_t)sg.in[0] + r * sg.in_stride[0];
+    const T* in1 = (const T*)(uintptr_t)sg.in[1] + r * sg.in_stride[1];
+    const T* in2 = (const T*)(uintptr_t)sg.in[2] + r * sg.in_stride[2];
+    const T w0 = (T)(int64_t)sg.w[0], w1 = (T)(int64_t)sg.w[1], w2 = (T)(int64_t)sg.w[2];
+    T* o = out + (size_t)g * (n + 1);
+    for (int w = lane; w <= n; w += 64) {
+        T acc = w == n ? (T)sg.cst : (T)0;
+        if (sg.nin > 0) acc += w0 * in0[w];
+        if (sg.nin > 1) acc += w1 * in1[w];
+        if (sg.nin > 2) acc += w2 * in2[w];
+        o[w] = acc;
+    }
+    if (lane == 0) {
+        out_ptrs[g] = sg.out + (uint64_t)(r * sg.out_stride) * sizeof(T);
+        tv_index[g] = sg.lut < 0 ? 0 : sg.lut;
+    }
+}
+
+}  // namespace
+
+int launch_combine(tfhe_ctx* c, const Segment* d_segs, const uint32_t* d_start, int nseg, uint32_t total,
+                   void* lwe_out, uint64_t* out_ptrs, int32_t* tv_index, hipStream_t s) {
+    if (!total) return TFHE_OK;
+    const unsigned grid = (total + 3) / 4;
+    if (c->q == 32)
+        hipLaunchKernelGGL(combine_kernel<uint32_t>, dim3(grid), dim3(256), 0, s, d_segs, d_start, nseg, total,
+                           (uint32_t*)lwe_out, out_ptrs, tv_index, (int)c->p.n);
+    else
+        hipLaunchKernelGGL(combine_kernel<uint64_t>, dim3(grid), dim3(256), 0, s, d_segs, d_start, nseg, total,
+                           (uint64_t*)lwe_out, out_ptrs, tv_index, (int)c->p.n);
+    return hip_check(c, hipGetLastError(), "launch combine");
+}
+
+// ------------------------------------------------------------- netlists
+
+namespace {
+
+struct Ref {  // a ciphertext operand: word address + row stride in words
+    uint64_t addr;
+    int64_t stride;
+};
+
+struct Copy {  // device-to-device copy done before a level's gates
+    uint64_t src, dst, bytes;
+};
+
+struct Level {
+    std::vector<Segment> segs;
+    std::vector<Copy> copies;
+};
+
+struct Netlist {
+    std::vector<Level> levels;
+    size_t tmp_words = 0;  // words of temporaries used (relative addresses)
+};
+
+// Temporaries are addressed relative to a base chosen at execution time:
+// the high bit marks a relative address, resolved when segments are uploaded.
+constexpr uint64_t REL = 1ull << 63;
+
+struct Builder {
+    tfhe_ctx* c;
+    size_t wb;
+    size_t lw;  // words per small LWE
+    Netlist net;
+
+    explicit Builder(tfhe_ctx* cc) : c(cc), wb(word_bytes(cc)), lw(cc->p.n + 1) {}
+
+    uint64_t eighth() const { return c->q == 32 ? (1ull << 29) : (1ull << 61); }
+    uint64_t wrap(int64_t v) const {
+        uint64_t u = (uint64_t)v;
+        return c->q == 32 ? (u & 0xFFFFFFFFull) : u;
+    }
+    Ref tmp(uint32_t rows) {
+        Ref r{REL | (net.tmp_words * wb), (int64_t)lw};
+        net.tmp_words += (size_t)rows * lw;
+        return r;
+    }
+    void level_push(size_t lev, const Segment& s) {
+        if (net.levels.size() <= lev) net.levels.resize(lev + 1);
+        net.levels[lev].segs.push_back(s);
+    }
+    void copy_push(size_t lev, uint64_t src, uint64_t dst, uint64_t bytes) {
+        if (net.levels.size() <= lev) net.levels.resize(lev + 1);
+        net.levels[lev].copies.push_back(Copy{src, dst, bytes});
+    }
+    // Gate on `rows` rows; operands given as refs (nullptr entries = FALSE constant).
+    void gate(size_t lev, int op, uint32_t rows, std::vector<const Ref*> ins, Ref out) {
+        GateForm f = gate_form(op);
+        Segment s{};
+        int64_t cst = (int64_t)f.c8;  // units of 1/8
+        int k = 0;
+        for (int j = 0; j < f.nin; j++) {
+            const Ref* r = ins[j];
+            if (!r) {  // trivial FALSE = (0, -1/8) contributes -w_j/8
+                cst -= f.w[j];
+                continue;
+            }
+            s.in[k] = r->addr;
+            s.in_stride[k] = r->stride;
+            s.w[k] = f.w[j];
+            k++;
+        }
+        s.nin = k;
+        s.cst = wrap(cst * (int64_t)eighth());
+        s.out = out.addr;
+        s.out_stride = out.stride;
+        s.rows = rows;
+        s.lut = -1;
+        level_push(lev, s);
+    }
+    void gate_w(size_t lev, uint32_t rows, std::vector<std::pair<const Ref*, int>> ins, int64_t cst8, Ref out) {
+        Segment s{};
+        int64_t cst = cst8;
+        int k = 0;
+        for (auto& pr : ins) {
+            if (!pr.first) { cst -= pr.second; continue; }
+            s.in[k] = pr.first->addr;
+            s.in_stride[k] = pr.first->stride;
+            s.w[k] = pr.second;
+            k++;
+        }
+        s.nin = k;
+        s.cst = wrap(cst * (int64_t)eighth());
+        s.out = out.addr;
+        s.out_stride = out.stride;
+        s.rows = rows;
+        s.lut = -1;
+        level_push(lev, s);
+    }
+
+    static Ref bit(const Ref& base, uint32_t j, size_t lw_, size_t wb_) {
+        return Ref{base.addr + (uint64_t)j * lw_ * wb_, base.stride};
+    }
+
+    // Returns the level after the last one used; the root output goes to `out`.
+    size_t eq(size_t lev, uint32_t rows, uint32_t w, const Ref& col, const Ref& lit, Ref out) {
+        std::vector<Ref> nodes;
+        for (uint32_t j = 0; j < w; j++) {
+            Ref a = bit(col, j, lw, wb), cj = bit(lit, j, lw, wb);
+            Ref o = w == 1 ? out : tmp(rows);
+            gate(lev, G_XNOR, rows, {&a, &cj}, o);
+            nodes.push_back(o);
+        }
+        lev++;
+        while (nodes.size() > 1) {
+            std::vector<Ref> nxt;
+            const size_t pairs = nodes.size() / 2;
+            for (size_t i = 0; i < pairs; i++) {
+                const bool root = nodes.size() == 2;
+                Ref o = root ? out : tmp(rows);
+                gate(lev, G_AND, rows, {&nodes[2 * i], &nodes[2 * i + 1]}, o);
+                nxt.push_back(o);
+            }
+            if (nodes.size() % 2) nxt.push_back(nodes.back());
+            nodes.swap(nxt);
+            lev++;
+        }
+        return lev;
+    }
+    // a < c as a borrow chain; swap = true computes c < a.
+    size_t lt(size_t lev, uint32_t rows, uint32_t w, const Ref& a, const Ref& cc, Ref out, bool swap) {
+        Ref prev{};
+        for (uint32_t j = 0; j < w; j++) {
+            Ref x = bit(swap ? cc : a, j, lw, wb), y = bit(swap ? a : cc, j, lw, wb);
+            Ref o = j + 1 == w ? out : tmp(rows);
+            // MAJ(not x, y, b) = -x + y + b; b_{-1} = FALSE
+            gate_w(lev + j, rows, {{&x, -1}, {&y, 1}, {j ? &prev : nullptr, 1}}, 0, o);
+            prev = o;
+        }
+        return lev + w;
+    }
+    size_t predicate(size_t lev, uint32_t rows, uint32_t w, int op, const Ref& col, const Ref& la,
+                     const Ref* lb, Ref out) {
+        switch (op) {
+            case SQL_OP_EQ: return eq(lev, rows, w, col, la, out);
+            case SQL_OP_LT: return lt(lev, rows, w, col, la, out, false);
+            case SQL_OP_GT: return lt(lev, rows, w, col, la, out, true);
+            case SQL_OP_BETWEEN: {
+                Ref b1 = tmp(rows), b2 = tmp(rows);
+                lt(lev, rows, w, col, la, b1, false);   // col < lo
+                lt(lev, rows, w, col, *lb, b2, true);   // hi < col
+                gate(lev + w, G_NOR, rows, {&b1, &b2}, out);
+                return lev + w + 1;
+            }
+        }
+        return lev;
+    }
+    size_t select(size_t lev, uint32_t rows, uint32_t w, const Ref& mask, const Ref& col, Ref out) {
+        for (uint32_t j = 0; j < w; j++) {
+            Ref cj = bit(col, j, lw, wb), oj = bit(out, j, lw, wb);
+            gate(lev, G_AND, rows, {&mask, &cj}, oj);
+        }
+        return lev + 1;
+    }
+};
+
+// ---------------------------------------------------------- execution
+
+struct Exec {
+    tfhe_ctx* c;
+    hipStream_t s;
+    size_t wb, lw, bw;
+    uint32_t max_batch;
+
+    Exec(tfhe_ctx* cc, hipStream_t ss) : c(cc), s(ss), wb(word_bytes(cc)), lw(cc->p.n + 1),
+                                          bw((size_t)cc->p.k * cc->p.N + 1), max_batch(65536) {}
+
+    // Lay out the workspace: temporaries, then per-level staging.
+    int run(Netlist& net, bool use_graph) {
+        size_t max_gates = 0, nseg_total = 0;
+        for (auto& lv : net.levels) {
+            size_t g = 0;
+            for (auto& sg : lv.segs) g += sg.rows;
+            max_gates = std::max(max_gates, g);
+            nseg_total += lv.segs.size();
+        }
+        if (!max_gates) return TFHE_OK;
+        const uint32_t chunk = (uint32_t)std::min<size_t>(max_gates, max_batch);
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        const size_t tmp_b = al(net.tmp_words * wb);
+        const size_t lwe_b = al((size_t)chunk * lw * wb);
+        const size_t big_b = al((size_t)chunk * bw * wb);
+        const size_t ptr_b = al((size_t)chunk * 8);
+        const size_t tvi_b = al((size_t)chunk * 4);
+        const size_t br_b = al(blind_rotate_ws_bytes(c, chunk));
+        // segments split into chunks: upper bound of pieces
+        std::vector<Segment> flat;
+        std::vector<uint32_t> starts;
+        struct Piece { size_t seg_off; int nseg; uint32_t total; size_t copy_off; int ncopy; };
+        std::vector<Piece> pieces;
+        std::vector<Copy> copies;
+        for (auto& L : net.levels) {
+            auto& lv = L.segs;
+            const size_t c0 = copies.size();
+            copies.insert(copies.end(), L.copies.begin(), L.copies.end());
+            bool first = true;
+            // split the level into chunks of at most `chunk` gates
+            size_t i = 0;
+            uint32_t carried = 0;  // rows of segment i already emitted
+            if (lv.empty() && !L.copies.empty()) pieces.push_back(Piece{flat.size(), 0, 0, c0, (int)L.copies.size()});
+            while (i < lv.size()) {
+                Piece pc{flat.size(), 0, 0, c0, first ? (int)L.copies.size() : 0};
+                first = false;
+                while (i < lv.size() && pc.total < chunk) {
+                    Segment sg = lv[i];
+                    const uint32_t take = std::min<uint32_t>(sg.rows - carried, chunk - pc.total);
+                    for (int j = 0; j < sg.nin; j++) sg.in[j] += (uint64_t)(carried * sg.in_stride[j]) * wb;
+                    sg.out += (uint64_t)(carried * sg.out_stride) * wb;
+                    sg.rows = take;
+                    flat.push_back(sg);
+                    starts.push_back(pc.total);
+                    pc.total += take;
+                    pc.nseg++;
+                    carried += take;
+                    if (carried == lv[i].rows) { i++; carried = 0; }
+                }
+                pieces.push_back(pc);
+            }
+        }
+        const size_t seg_b = al(flat.size() * sizeof(Segment));
+        const size_t st_b = al(starts.size() * 4);
+        const size_t total = tmp_b + lwe_b + big_b + ptr_b + tvi_b + br_b + seg_b + st_b;
+        int rc = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
+        if (rc) return rc;
+        if ((rc = ctx_reserve(c, total))) return rc;
+        uint8_t* base = (uint8_t*)c->ws;
+        uint8_t* tmp = base;
+        uint8_t* lwe = tmp + tmp_b;
+        uint8_t* big = lwe + lwe_b;
+        uint64_t* ptrs = (uint64_t*)(big + big_b);
+        int32_t* tvi = (int32_t*)((uint8_t*)ptrs + ptr_b);
+        uint8_t* brws = (uint8_t*)tvi + tvi_b;
+        Segment* dsegs = (Segment*)(brws + br_b);
+        uint32_t* dstart = (uint32_t*)((uint8_t*)dsegs + seg_b);
+        auto resolve = [&](uint64_t a) -> uint64_t { return (a & REL) ? (uint64_t)(uintptr_t)tmp + (a & ~REL) : a; };
+        for (auto& sg : flat) {
+            for (int j = 0; j < 3; j++) sg.in[j] = j < sg.nin ? resolve(sg.in[j]) : 0;
+            sg.out = resolve(sg.out);
+        }
+        if ((rc = hip_check(c, hipMemcpy(dsegs, flat.data(), flat.size() * sizeof(Segment), hipMemcpyHostToDevice), "upload segments")))
+            return rc;
+        if ((rc = hip_check(c, hipMemcpy(dstart, starts.data(), starts.size() * 4, hipMemcpyHostToDevice), "upload starts")))
+            return rc;
+
+        hipStream_t rs = s;
+        hipStream_t cap = nullptr;
+        hipGraph_t graph = nullptr;
+        if (use_graph) {
+            if ((rc = hip_check(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "create capture stream"))) return rc;
+            if ((rc = hip_check(c, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture"))) {
+                hipStreamDestroy(cap);
+                return rc;
+            }
+            rs = cap;
+        }
+        for (auto& cp : copies) {
+            cp.src = resolve(cp.src);
+            cp.dst = resolve(cp.dst);
+        }
+        for (auto& pc : pieces) {
+            for (int k = 0; k < pc.ncopy && !rc; k++) {
+                const Copy& cp = copies[pc.copy_off + k];
+                rc = hip_check(c, hipMemcpyAsync((void*)(uintptr_t)cp.dst, (const void*)(uintptr_t)cp.src, cp.bytes,
+                                                 hipMemcpyDeviceToDevice, rs), "level copy");
+            }
+            if (rc) break;
+            if (!pc.total) continue;
+            if ((rc = launch_combine(c, dsegs + pc.seg_off, dstart + pc.seg_off, pc.nseg, pc.total, lwe, ptrs, tvi, rs))) break;
+            if ((rc = launch_blind_rotate(c, lwe, nullptr, nullptr, big, pc.total, brws, rs))) break;
+            if ((rc = launch_keyswitch(c, big, nullptr, ptrs, pc.total, rs))) break;
+        }
+        if (use_graph) {
+            hipError_t e = hipStreamEndCapture(cap, &graph);
+            if (!rc) rc = hip_check(c, e, "end capture");
+            hipGraphExec_t exec = nullptr;
+            if (!rc) rc = hip_check(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+            if (!rc) rc = hip_check(c, hipGraphLaunch(exec, s), "graph launch");
+            if (!rc) rc = hip_check(c, hipStreamSynchronize(s), "graph sync");
+            if (exec) hipGraphExecDestroy(exec);
+            if (graph) hipGraphDestroy(graph);
+            hipStreamDestroy(cap);
+        }
+        return rc;
+    }
+};
+
+Ref dev(const void* p, size_t stride_words) { return Ref{(uint64_t)(uintptr_t)p, (int64_t)stride_words}; }
+
+}  // namespace
+
+// ------------------------------------------------------------ C ABI
+
+extern "C" int tfhe_gate_batch(tfhe_ctx* c, int op, const void* d_x, const void* d_y, const void* d_z, void* d_out,
+                               uint32_t B, void* stream) {
+    if (!c) return TFHE_EINVAL;
+    if (op < G_AND || op > G_MAJ) return ctx_fail(c, TFHE_EINVAL, "unknown gate");
+    if (!B) return TFHE_OK;
+    if (!d_x || !d_y || !d_out || (op == G_MAJ && !d_z)) return ctx_fail(c, TFHE_EINVAL, "null ciphertext pointer");
+    Builder b(c);
+    const size_t lw = b.lw;
+    Ref x = dev(d_x, lw), y = dev(d_y, lw), z = dev(d_z, lw), o = dev(d_out, lw);
+    if (op == G_MAJ) b.gate(0, op, B, {&x, &y, &z}, o);
+    else b.gate(0, op, B, {&x, &y}, o);
+    Exec ex(c, (hipStream_t)stream);
+    return ex.run(b.net, false);
+}
+
+static int check_scan(tfhe_ctx* c, const void* col, uint32_t w, int op, const void* la, const void* lb, const void* mask) {
+    if (!col || !la || !mask) return ctx_fail(c, TFHE_EINVAL, "null ciphertext pointer");
+    if (w < 1 || w > 64) return ctx_fail(c, TFHE_ESHAPE, "column width must be 1..64 bits");
+    if (op < SQL_OP_EQ || op > SQL_OP_BETWEEN) return ctx_fail(c, TFHE_EINVAL, "unknown SQL operator");
+    if (op == SQL_OP_BETWEEN && !lb) return ctx_fail(c, TFHE_EINVAL, "BETWEEN needs an upper literal");
+    return TFHE_OK;
+}
+
+extern "C" int sql_mask_scan(tfhe_ctx* c, const void* d_col, uint32_t rows, uint32_t w, int op, const void* d_lit_a,
+                             const void* d_lit_b, void* d_mask, void* stream) {
+    if (!c) return TFHE_EINVAL;
+    if (!rows) return TFHE_OK;
+    int rc = check_scan(c, d_col, w, op, d_lit_a, d_lit_b, d_mask);
+    if (rc) return rc;
+    Builder b(c);
+    const size_t lw = b.lw;
+    Ref col = dev(d_col, (size_t)w * lw), la = dev(d_lit_a, 0), lb = dev(d_lit_b, 0), m = dev(d_mask, lw);
+    b.predicate(0, rows, w, op, col, la, d_lit_b ? &lb : nullptr, m);
+    Exec ex(c, (hipStream_t)stream);
+    return ex.run(b.net, false);
+}
+
+extern "C" int sql_masked_select(tfhe_ctx* c, const void* d_mask, const void* d_col, uint32_t rows, uint32_t w,
+                                 void* d_out, void* stream) {
+    if (!c) return TFHE_EINVAL;
+    if (!rows) return TFHE_OK;
+    if (!d_mask || !d_col || !d_out) return ctx_fail(c, TFHE_EINVAL, "null ciphertext pointer");
+    if (w < 1 || w > 64) return ctx_fail(c, TFHE_ESHAPE, "column width must be 1..64 bits");
+    Builder b(c);
+    const size_t lw = b.lw;
+    b.select(0, rows, w, dev(d_mask, lw), dev(d_col, (size_t)w * lw), dev(d_out, (size_t)w * lw));
+    Exec ex(c, (hipStream_t)stream);
+    return ex.run(b.net, false);
+}
+
+extern "C" int sql_scan_batch(tfhe_ctx* c, const sql_table_query* q, uint32_t count, int use_graph, void* stream) {
+    if (!c) return TFHE_EINVAL;
+    if (!count) return TFHE_OK;
+    if (!q) return ctx_fail(c, TFHE_EINVAL, "null query array");
+    Builder b(c);
+    const size_t lw = b.lw;
+    for (uint32_t t = 0; t < count; t++) {
+        const sql_table_query& Q = q[t];
+        if (!Q.rows) continue;
+        int rc = check_scan(c, Q.d_col, Q.w, Q.op, Q.d_lit_a, Q.d_lit_b, Q.d_mask);
+        if (rc) return rc;
+        Ref col = dev(Q.d_col, (size_t)Q.w * lw), la = dev(Q.d_lit_a, 0), lb = dev(Q.d_lit_b, 0), m = dev(Q.d_mask, lw);
+        const size_t lev = b.predicate(0, Q.rows, Q.w, Q.op, col, la, Q.d_lit_b ? &lb : nullptr, m);
+        if (Q.d_sel_col && Q.d_sel_out)
+            b.select(lev, Q.rows, Q.w, m, dev(Q.d_sel_col, (size_t)Q.w * lw), dev(Q.d_sel_out, (size_t)Q.w * lw));
+    }
+    Exec ex(c, (hipStream_t)stream);
+    return ex.run(b.net, use_graph != 0);
+}
+
+extern "C" int sql_masked_sum(tfhe_ctx* c, const void* d_mask, const void* d_col, uint32_t rows, uint32_t w,
+                              void* d_sum, uint32_t* width_out, void* stream) {
+    if (!c) return TFHE_EINVAL;
+    if (!d_mask || !d_col || !d_sum) return ctx_fail(c, TFHE_EINVAL, "null ciphertext pointer");
+    if (w < 1 || w > 32) return ctx_fail(c, TFHE_ESHAPE, "column width must be 1..32 bits");
+    if (!rows) return ctx_fail(c, TFHE_ESHAPE, "SUM needs at least one row");
+    Builder b(c);
+    const size_t lw = b.lw, wb = b.wb;
+    uint32_t width = w;
+    uint32_t final_w = w;
+    for (uint32_t r = rows; r > 1; r = (r + 1) / 2) final_w++;
+    if (width_out) *width_out = final_w;
+    // level 0: masked select into a [rows][w] operand buffer
+    Ref cur = b.tmp(rows * w);
+    cur.stride = (int64_t)(w * lw);
+    size_t lev = b.select(0, rows, w, dev(d_mask, lw), dev(d_col, (size_t)w * lw), cur);
+    uint32_t cnt = rows;
+    auto at = [&](const Ref& base, uint32_t op, uint32_t j, int64_t stride) -> Ref {
+        return Ref{base.addr + ((uint64_t)op * base.stride + (uint64_t)j * lw) * wb, stride};
+    };
+    while (cnt > 1) {
+        const uint32_t pairs = cnt / 2;
+        const bool odd = cnt & 1;
+        const uint32_t nw = width + 1;
+        const bool last = (pairs + (odd ? 1 : 0)) == 1;
+        Ref res;
+        if (last) res = Ref{(uint64_t)(uintptr_t)d_sum, (int64_t)(nw * lw)};
+        else { res = b.tmp((pairs + (odd ? 1 : 0)) * nw); res.stride = (int64_t)(nw * lw); }
+        const int64_t xs = 2 * cur.stride;  // pair stride
+        Ref x0 = at(cur, 0, 0, xs), y0 = at(cur, 1, 0, xs);
+        Ref carry = width == 1 ? at(res, 0, 1, res.stride) : b.tmp(pairs);
+        b.gate(lev, G_XOR, pairs, {&x0, &y0}, at(res, 0, 0, res.stride));
+        b.gate(lev, G_AND, pairs, {&x0, &y0}, carry);
+        Ref tb = b.tmp(pairs * width);
+        tb.stride = (int64_t)(width * lw);
+        for (uint32_t j = 1; j < width; j++) {
+            Ref xj = at(cur, 0, j, xs), yj = at(cur, 1, j, xs);
+            b.gate(lev, G_XOR, pairs, {&xj, &yj}, at(tb, 0, j, tb.stride));
+        }
+        for (uint32_t j = 1; j < width; j++) {
+            Ref xj = at(cur, 0, j, xs), yj = at(cur, 1, j, xs);
+            Ref tj = at(tb, 0, j, tb.stride);
+            Ref nc = j + 1 == width ? at(res, 0, width, res.stride) : b.tmp(pairs);
+            b.gate(lev + j, G_XOR, pairs, {&tj, &carry}, at(res, 0, j, res.stride));
+            b.gate(lev + j, G_MAJ, pairs, {&xj, &yj, &carry}, nc);
+            carry = nc;
+        }
+        if (odd) {
+            // the last operand passes up unchanged, zero-extended by a trivial FALSE
+            const Ref src = at(cur, cnt - 1, 0, 0), dst = at(res, pairs, 0, 0);
+            b.copy_push(lev, src.addr, dst.addr, (uint64_t)width * lw * wb);
+            b.copy_push(lev, (uint64_t)(uintptr_t)c->d_false, at(res, pairs, width, 0).addr, lw * wb);
+        }
+        lev += width;
+        cnt = pairs + (odd ? 1 : 0);
+        width = nw;
+        cur = res;
+    }
+    if (rows == 1) {
+        // a single row: the sum is the selected value itself
+        b.copy_push(lev, cur.addr, (uint64_t)(uintptr_t)d_sum, (uint64_t)w * lw * wb);
+    }
+    Exec ex(c, (hipStream_t)stream);
+    return ex.run(b.net, false);
+}

@@ -1,0 +1,276 @@
+"""GPU parity: every ciphertext the HIP library produces through the C ABI is
+compared word for word with the CPU oracle on the same seeded keys and inputs
+(the arithmetic is integer, so the tolerance is zero)."""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+from oracle import circuits as C
+from helpers import enc_bits, dec_bits, bits_to_int
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2510_15413_amd as fs  # noqa: E402
+from gpu_util import to_dev, from_dev, context, empty  # noqa: E402
+
+KERNELS = ["mfma", "plain"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+_KEYS = {}
+_CTX = {}
+
+
+def keys_for(pname):
+    if pname not in _KEYS:
+        p = si.PARAMS[pname]
+        _KEYS[pname] = oracle.Keys(p, si.KEY_SEED_BASE + 7)
+    return _KEYS[pname]
+
+
+def ctx_for(pname):
+    if pname not in _CTX:
+        _CTX[pname] = context(si.PARAMS[pname], keys_for(pname))
+    return _CTX[pname]
+
+
+def rand_lwe(p, count, seed):
+    return si.torus(seed, 99, count * (p.n + 1), p.q).reshape(count, p.n + 1)
+
+
+# ------------------------------------------------------------ key material
+
+@pytest.mark.parametrize("pname", ["tiny", "toy", "tiny64"])
+def test_device_keygen_matches_oracle(pname):
+    p = si.PARAMS[pname]
+    say("keygen", pname)
+    K = keys_for(pname)
+    s, S, bsk, ksk = fs.tfhe_keygen(p, K.seed)
+    torch.cuda.synchronize()
+    assert np.array_equal(from_dev(p, s), K.s)
+    assert np.array_equal(from_dev(p, S), K.S)
+    assert np.array_equal(from_dev(p, bsk), K.bsk.ravel())
+    assert np.array_equal(from_dev(p, ksk), K.ksk.ravel())
+
+
+@pytest.mark.parametrize("pname", ["toy", "tiny64"])
+def test_device_encrypt_and_phase_match_oracle(pname):
+    p = si.PARAMS[pname]
+    K = keys_for(pname)
+    count, start, tag_hi = 37, 5, 3
+    mus = si.torus(4, 9, count, p.q)
+    masks, errs = si.lwe_randomness(p, 21, count, tag_hi=tag_hi, start=start)
+    want = oracle.lwe_encrypt(p, K.s, masks, errs, mus)
+    got = fs.tfhe_lwe_encrypt(p, 21, to_dev(p, K.s), to_dev(p, mus), start=start, tag_hi=tag_hi)
+    assert np.array_equal(from_dev(p, got), want)
+    ph = from_dev(p, fs.tfhe_lwe_phase(p, to_dev(p, K.s), got))
+    assert [int(v) for v in ph] == [oracle.lwe_phase(p.q, K.s, c) for c in want]
+
+
+def test_device_rng_matches_seeded_inputs():
+    got = fs.tfhe_rng_fill(1234, 77, 1000, start=33).cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, si.raw(1234, 77, 1000, start=33))
+
+
+# ------------------------------------------------------------- bootstrapping
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("pname", ["tiny", "toy", "tiny64"])
+@pytest.mark.parametrize("B", [1, 17, 40])
+def test_bootstrap_parity(kernel, pname, B):
+    p = si.PARAMS[pname]
+    K = keys_for(pname)
+    ctx = ctx_for(pname)
+    ctx.set_kernel(kernel)
+    say("bootstrap", kernel, pname, B)
+    lwe = rand_lwe(p, B, 1000 + B)
+    out = empty(p, B, p.k * p.N + 1)
+    ctx.tfhe_bootstrap_batch(to_dev(p, lwe), out)
+    # a random test polynomial too
+    tv = si.torus(77, 5, p.N, p.q)
+    out2 = empty(p, B, p.k * p.N + 1)
+    ctx.tfhe_bootstrap_batch(to_dev(p, lwe), out2, testv=to_dev(p, tv))
+    torch.cuda.synchronize()
+    g1, g2 = from_dev(p, out), from_dev(p, out2)
+    gtv = oracle.gate_testv(p)
+    idx = list(range(B)) if B <= 17 else [0, 1, 15, 16, 17, 31, 32, B - 1]
+    want = oracle.parallel_map(lambda i: (oracle.bootstrap(p, K.bsk, lwe[i], gtv),
+                                          oracle.bootstrap(p, K.bsk, lwe[i], tv)), idx)
+    for i, (w1, w2) in zip(idx, want):
+        assert np.array_equal(g1[i], w1), (kernel, pname, B, i)
+        assert np.array_equal(g2[i], w2), (kernel, pname, B, i)
+    ctx.set_kernel("mfma")
+
+
+@pytest.mark.parametrize("pname", ["tiny", "toy", "tiny64"])
+def test_keyswitch_parity(pname):
+    p = si.PARAMS[pname]
+    K = keys_for(pname)
+    ctx = ctx_for(pname)
+    B = 70
+    big = si.torus(5, 98, B * (p.k * p.N + 1), p.q).reshape(B, p.k * p.N + 1)
+    out = empty(p, B, p.n + 1)
+    ctx.tfhe_keyswitch_batch(to_dev(p, big), out)
+    torch.cuda.synchronize()
+    g = from_dev(p, out)
+    for i in range(B):
+        assert np.array_equal(g[i], oracle.keyswitch(p, K.ksk, big[i])), i
+
+
+@pytest.mark.parametrize("op", list(C.GATES))
+def test_gate_batch_parity(op):
+    p = si.TOY
+    K = keys_for("toy")
+    ctx = ctx_for("toy")
+    B = 12
+    bits = si.bits(31, 1, 3 * B).reshape(3, B)
+    X = [enc_bits(p, K, bits[j], 300 + j) for j in range(3)]
+    out = empty(p, B, p.n + 1)
+    ctx.tfhe_gate_batch(op, to_dev(p, X[0]), to_dev(p, X[1]), out,
+                        z=to_dev(p, X[2]) if op == "MAJ" else None)
+    torch.cuda.synchronize()
+    g = from_dev(p, out)
+    nin = 3 if op == "MAJ" else 2
+    want = C.gate_batch(p, K, op, [[X[j][i] for j in range(nin)] for i in range(B)])
+    assert np.array_equal(g, want)
+    pb = C.PlainBackend()
+    assert dec_bits(p, K, g).tolist() == [int(pb.gate(op, *[bits[j][i] for j in range(nin)])) for i in range(B)]
+
+
+# --------------------------------------------------------------- SQL circuits
+
+def _table(p, K, rows, w, seed, table_id=0):
+    col1, col2 = si.table(si.DATA_SEED_BASE + seed, rows, w, table_id)
+    c1 = enc_bits(p, K, si.column_bits(col1, w), seed * 10 + 1, tag_hi=table_id).reshape(rows, w, p.n + 1)
+    c2 = enc_bits(p, K, si.column_bits(col2, w), seed * 10 + 2, tag_hi=table_id).reshape(rows, w, p.n + 1)
+    return col1, col2, c1, c2
+
+
+def _lit(p, K, v, w, seed):
+    return enc_bits(p, K, [(int(v) >> j) & 1 for j in range(w)], seed)
+
+
+def test_toy_query_full_parity():
+    """32 rows of 4-bit columns: mask(col1 == 7) (4 XNOR + 3 AND per row), then
+    mask AND each bit of col2: all 352 bootstrap outputs bit-exact."""
+    p = si.TOY
+    K = keys_for("toy")
+    ctx = ctx_for("toy")
+    rows, w = 32, 4
+    col1, col2, c1, c2 = _table(p, K, rows, w, 1)
+    lit = _lit(p, K, 7, w, 77)
+    mask, sel = empty(p, rows, p.n + 1), empty(p, rows, w, p.n + 1)
+    ctx.sql_mask_scan(to_dev(p, c1), rows, w, "eq", to_dev(p, lit), mask)
+    ctx.sql_masked_select(mask, to_dev(p, c2), rows, w, sel)
+    torch.cuda.synchronize()
+    om = C.mask_rows(p, K, "eq", c1, lit)
+    osel = C.select_rows(p, K, om, c2)
+    assert np.array_equal(from_dev(p, mask), om)
+    assert np.array_equal(from_dev(p, sel), osel)
+    assert dec_bits(p, K, om).tolist() == [int(v == 7) for v in col1]
+    got = [bits_to_int(b) for b in dec_bits(p, K, osel)]
+    assert got == [int(b) if a == 7 else 0 for a, b in zip(col1, col2)]
+
+
+@pytest.mark.parametrize("op", ["lt", "gt", "between", "eq"])
+def test_toy_predicates_parity(op):
+    p = si.TOY
+    K = keys_for("toy")
+    ctx = ctx_for("toy")
+    rows, w = 13, 5
+    col1, col2, c1, c2 = _table(p, K, rows, w, 2)
+    lo, hi = 9, 22
+    la = _lit(p, K, lo if op == "between" else int(col1[3]), w, 81)
+    lb = _lit(p, K, hi, w, 82) if op == "between" else None
+    mask = empty(p, rows, p.n + 1)
+    ctx.sql_mask_scan(to_dev(p, c1), rows, w, op, to_dev(p, la), mask,
+                      lit_b=to_dev(p, lb) if lb is not None else None)
+    torch.cuda.synchronize()
+    om = C.mask_rows(p, K, op, c1, la, lb)
+    assert np.array_equal(from_dev(p, mask), om)
+    c = lo if op == "between" else int(col1[3])
+    truth = {"eq": lambda a: a == c, "lt": lambda a: a < c, "gt": lambda a: a > c,
+             "between": lambda a: lo <= a <= hi}[op]
+    assert dec_bits(p, K, om).tolist() == [int(truth(int(a))) for a in col1]
+
+
+@pytest.mark.parametrize("rows", [1, 2, 5, 8])
+def test_masked_sum_parity(rows):
+    p = si.TINY
+    K = keys_for("tiny")
+    ctx = ctx_for("tiny")
+    w = 3
+    col1, col2, c1, c2 = _table(p, K, rows, w, 3)
+    m_bits = [(i * 7 + 1) % 3 != 0 for i in range(rows)]
+    m = enc_bits(p, K, m_bits, 55)
+    width = fs.sum_width(w, rows)
+    out = empty(p, width, p.n + 1)
+    got_w = ctx.sql_masked_sum(to_dev(p, m), to_dev(p, c2), rows, w, out)
+    torch.cuda.synchronize()
+    assert got_w == width
+    be = C.CipherBackend(p, K)
+    sel = [C.select(be, m[r], list(c2[r])) for r in range(rows)]
+    want = np.stack(C.sum_tree(be, sel)) if rows > 1 else np.stack(sel[0])
+    assert np.array_equal(from_dev(p, out), want)
+    assert bits_to_int(dec_bits(p, K, want)) == sum(int(v) for v, b in zip(col2, m_bits) if b)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_scan_batch_isolation_and_parity(use_graph):
+    """Uneven tables with mixed predicates in one level-batched schedule give the
+    same bits as each table alone, and match the oracle."""
+    p = si.TOY
+    K = keys_for("toy")
+    ctx = ctx_for("toy")
+    w = 4
+    specs = [(5, "eq"), (17, "lt"), (9, "between")]
+    qs, alone, tabs = [], [], []
+    for t, (rows, op) in enumerate(specs):
+        col1, col2, c1, c2 = _table(p, K, rows, w, 10 + t, table_id=t)
+        la = _lit(p, K, int(col1[0]) if op == "eq" else 6, w, 90 + t)
+        lb = _lit(p, K, 12, w, 95 + t) if op == "between" else None
+        d = dict(col=to_dev(p, c1), sel_col=to_dev(p, c2), rows=rows, w=w, op=op, lit_a=to_dev(p, la),
+                 lit_b=to_dev(p, lb) if lb is not None else None, mask=empty(p, rows, p.n + 1),
+                 sel_out=empty(p, rows, w, p.n + 1))
+        qs.append(d)
+        tabs.append((col1, col2, c1, c2, la, lb))
+        m1, s1 = empty(p, rows, p.n + 1), empty(p, rows, w, p.n + 1)
+        ctx.sql_mask_scan(d["col"], rows, w, op, d["lit_a"], m1, lit_b=d["lit_b"])
+        ctx.sql_masked_select(m1, d["sel_col"], rows, w, s1)
+        alone.append((m1, s1))
+    ctx.sql_scan_batch(qs, use_graph=use_graph)
+    torch.cuda.synchronize()
+    for t, (d, (m1, s1)) in enumerate(zip(qs, alone)):
+        assert torch.equal(d["mask"], m1), t
+        assert torch.equal(d["sel_out"], s1), t
+    # oracle end to end on the first two rows of every table
+    for t, (d, (col1, col2, c1, c2, la, lb)) in enumerate(zip(qs, tabs)):
+        op = specs[t][1]
+        om = C.mask_rows(p, K, op, c1[:2], la, lb)
+        assert np.array_equal(from_dev(p, d["mask"])[:2], om), t
+        assert np.array_equal(from_dev(p, d["sel_out"])[:2], C.select_rows(p, K, om, c2[:2])), t
+
+
+def test_errors_are_reported():
+    p = si.TOY
+    ctx = ctx_for("toy")
+    x = empty(p, 4, p.n + 1)
+    with pytest.raises(fs.FheError):
+        ctx.sql_mask_scan(x, 4, 0, "eq", x, x)
+    bad = si.Params("bad", 32, 64, 2, 256, 8, 2, 2, 5, 20, 25)
+    with pytest.raises(fs.FheError):
+        fs.Context(bad, np.zeros(10, dtype=np.uint64), np.zeros(10, dtype=np.uint64))
+    # B = 0 is a no-op
+    ctx.tfhe_bootstrap_batch(x, x, B=0)
