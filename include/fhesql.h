@@ -152,6 +152,17 @@ typedef struct sql_table_query {
 int sql_scan_batch(tfhe_ctx* ctx, const sql_table_query* q, uint32_t count, int use_graph,
                    void* hip_stream);
 
+/* Kernel timing.  While enabled (on != 0), every blind-rotation and
+ * key-switching kernel launched by this context is bracketed by HIP events
+ * recorded on the stream it runs on (not during graph capture).  Enabling
+ * clears the counters.  tfhe_timing_read synchronizes the events and returns,
+ * per kernel kind (0 = blind rotation, 1 = key switching), the number of
+ * launches, the summed kernel time in milliseconds and the summed batch size
+ * (ciphertexts).  Any pointer may be NULL. */
+int tfhe_timing_enable(tfhe_ctx* ctx, int on);
+int tfhe_timing_read(tfhe_ctx* ctx, int kind, uint64_t* launches, double* total_ms,
+                     uint64_t* cts);
+
 /* ---- client-side helpers on the device (synthetic data and checks) ---- */
 
 /* Counter-based SplitMix64 stream: value i of (seed, tag) is

@@ -31,7 +31,7 @@ EXPORTS = [
     "tfhe_last_error", "tfhe_set_kernel", "tfhe_ctx_sync", "tfhe_bootstrap_batch",
     "tfhe_keyswitch_batch", "tfhe_gate_batch", "sql_mask_scan", "sql_masked_select",
     "sql_masked_sum", "sql_scan_batch", "tfhe_rng_fill", "tfhe_keygen",
-    "tfhe_lwe_encrypt", "tfhe_lwe_phase",
+    "tfhe_lwe_encrypt", "tfhe_lwe_phase", "tfhe_timing_enable", "tfhe_timing_read",
 ]
 
 
@@ -83,6 +83,9 @@ def load():
         "tfhe_keygen": (i32, [P, u64, u32, u32, vp, vp, vp, vp, vp]),
         "tfhe_lwe_encrypt": (i32, [P, u64, u64, u64, u32, u64, vp, vp, vp, u64, u32, vp]),
         "tfhe_lwe_phase": (i32, [P, vp, vp, vp, u64, u32, vp]),
+        "tfhe_timing_enable": (i32, [vp, i32]),
+        "tfhe_timing_read": (i32, [vp, i32, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(u64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -165,6 +168,17 @@ class Context:
         if rc != 0:
             msg = load().tfhe_last_error(self._h)
             raise FheError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+    # -- kernel timing ----------------------------------------------------
+    def timing_enable(self, on=True):
+        self._rc(load().tfhe_timing_enable(self._h, 1 if on else 0), "tfhe_timing_enable")
+
+    def timing_read(self, kind):
+        """(launches, total_ms, cts) of kind 'br' (blind rotation) or 'ks'."""
+        n, ms, cts = ctypes.c_uint64(), ctypes.c_double(), ctypes.c_uint64()
+        self._rc(load().tfhe_timing_read(self._h, 0 if kind == "br" else 1, ctypes.byref(n), ctypes.byref(ms),
+                                         ctypes.byref(cts)), "tfhe_timing_read")
+        return n.value, ms.value, cts.value
 
     # -- evaluation -------------------------------------------------------
     def set_kernel(self, kind):

@@ -10,7 +10,7 @@ SOURCES = ["ctx.hip", "br_mfma.hip", "br_plain.hip", "keyswitch.hip", "sql.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-result", "-Wno-unused-variable"]
+         "-Wall", "-Wno-unused-result", "-Wno-unused-variable", "-Wno-unused-value"]
 
 
 def build(jobs: int = 5, verbose: bool = False) -> str:

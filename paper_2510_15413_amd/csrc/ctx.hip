@@ -10,6 +10,7 @@ int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_
 int launch_br_plain(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_t* tv_index,
                     void* big_out, uint32_t B, hipStream_t s);
 size_t mfma_ws_bytes(const tfhe_ctx* c, uint32_t B);
+static int timing_drain(tfhe_ctx* c);
 
 int ctx_fail(tfhe_ctx* c, int code, const std::string& msg) {
     if (c) c->err = msg;
@@ -167,6 +168,8 @@ extern "C" int tfhe_ctx_create(const tfhe_params* p, const void* bsk, size_t bsk
 extern "C" void tfhe_ctx_destroy(tfhe_ctx* c) {
     if (!c) return;
     hipDeviceSynchronize();
+    timing_drain(c);
+    for (auto e : c->event_pool) hipEventDestroy(e);
     if (c->d_bsk) hipFree(c->d_bsk);
     if (c->d_bsk8) hipFree(c->d_bsk8);
     if (c->d_ksk) hipFree(c->d_ksk);
@@ -190,6 +193,73 @@ extern "C" int tfhe_ctx_sync(tfhe_ctx* c, void* stream) {
     return hip_check(c, hipStreamSynchronize((hipStream_t)stream), "stream synchronize");
 }
 
+// ---------------------------------------------------------------- timing
+
+static hipEvent_t pool_get(tfhe_ctx* c) {
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+TimedLaunch::TimedLaunch(tfhe_ctx* cc, hipStream_t ss, int k, uint32_t n) : c(cc), s(ss), kind(k), cts(n) {
+    if (!c->timing || capturing(s)) return;
+    a = pool_get(c);
+    b = pool_get(c);
+    if (a && b) hipEventRecord(a, s);
+}
+
+TimedLaunch::~TimedLaunch() {
+    if (!a || !b) return;
+    hipEventRecord(b, s);
+    c->timed.push_back(tfhe_ctx::Timed{a, b, kind, cts});
+}
+
+static int timing_drain(tfhe_ctx* c) {
+    for (auto& t : c->timed) {
+        float ms = 0;
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e != hipSuccess) return hip_check(c, e, "timing event");
+        hipEventElapsedTime(&ms, t.a, t.b);
+        c->t_launch[t.kind]++;
+        c->t_ms[t.kind] += ms;
+        c->t_cts[t.kind] += t.cts;
+        c->event_pool.push_back(t.a);
+        c->event_pool.push_back(t.b);
+    }
+    c->timed.clear();
+    return TFHE_OK;
+}
+
+extern "C" int tfhe_timing_enable(tfhe_ctx* c, int on) {
+    if (!c) return TFHE_EINVAL;
+    int rc = timing_drain(c);
+    if (rc) return rc;
+    c->timing = on != 0;
+    for (int k = 0; k < 2; k++) { c->t_launch[k] = 0; c->t_ms[k] = 0; c->t_cts[k] = 0; }
+    return TFHE_OK;
+}
+
+extern "C" int tfhe_timing_read(tfhe_ctx* c, int kind, uint64_t* launches, double* total_ms, uint64_t* cts) {
+    if (!c || kind < 0 || kind > 1) return TFHE_EINVAL;
+    int rc = timing_drain(c);
+    if (rc) return rc;
+    if (launches) *launches = c->t_launch[kind];
+    if (total_ms) *total_ms = c->t_ms[kind];
+    if (cts) *cts = c->t_cts[kind];
+    return TFHE_OK;
+}
+
 size_t blind_rotate_ws_bytes(const tfhe_ctx* c, uint32_t B) {
     return c->kernel == TFHE_KERNEL_MFMA ? mfma_ws_bytes(c, B) : 0;
 }
@@ -198,6 +268,7 @@ int launch_blind_rotate(tfhe_ctx* c, const void* lwe_in, const void* testv_table
                         void* big_out, uint32_t B, void* ws, hipStream_t s) {
     if (B == 0) return TFHE_OK;
     const void* tv = testv_table ? testv_table : c->d_gate_tv;
+    TimedLaunch tl(c, s, 0, B);
     if (c->kernel == TFHE_KERNEL_PLAIN) return launch_br_plain(c, lwe_in, tv, tv_index, big_out, B, s);
     return launch_br_mfma(c, lwe_in, tv, tv_index, big_out, B, ws, s);
 }

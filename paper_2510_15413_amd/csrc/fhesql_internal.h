@@ -140,6 +140,28 @@ struct tfhe_ctx {
     size_t ws_bytes = 0;
     std::string err;
     hipDeviceProp_t prop{};
+    // kernel timing (per kind: 0 blind rotation, 1 key switching)
+    bool timing = false;
+    struct Timed {
+        hipEvent_t a, b;
+        int kind;
+        uint32_t cts;
+    };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> event_pool;
+    uint64_t t_launch[2] = {0, 0}, t_cts[2] = {0, 0};
+    double t_ms[2] = {0, 0};
+};
+
+// Records an event pair around one launch when timing is enabled.
+struct TimedLaunch {
+    tfhe_ctx* c;
+    hipStream_t s;
+    int kind;
+    uint32_t cts;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(tfhe_ctx* cc, hipStream_t ss, int k, uint32_t n);
+    ~TimedLaunch();
 };
 
 int ctx_fail(tfhe_ctx* c, int code, const std::string& msg);

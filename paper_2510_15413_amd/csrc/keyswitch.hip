@@ -95,6 +95,7 @@ int launch_ks_t(tfhe_ctx* c, const void* big, void* out, const uint64_t* out_ptr
 int launch_keyswitch(tfhe_ctx* c, const void* big_in, void* out, const uint64_t* out_ptrs, uint32_t B,
                      hipStream_t s) {
     if (B == 0) return TFHE_OK;
+    TimedLaunch tl(c, s, 1, B);
     return c->q == 32 ? launch_ks_t<uint32_t>(c, big_in, out, out_ptrs, B, s)
                       : launch_ks_t<uint64_t>(c, big_in, out, out_ptrs, B, s);
 }

@@ -1,0 +1,122 @@
+"""GPU parity at the standard 32-bit gate parameters (n=630, N=1024, l=3,
+Bg=2^7, key switching 2^2 x 8) in the launch configuration the benchmark
+times: bootstraps of a 4096-ciphertext batch and the 4096-row scan, checked
+word for word against the oracle on sampled outputs (the oracle needs ~4 s
+per bootstrap here), plus decryption of every row."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+from oracle import circuits as C
+from helpers import enc_bits, bits_to_int
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2510_15413_amd as fs  # noqa: E402
+from gpu_util import to_dev, from_dev, empty  # noqa: E402
+
+P = si.STD
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def std():
+    say("oracle keygen at n=630, N=1024")
+    K = oracle.Keys(P, si.KEY_SEED_BASE + 2)
+    ctx = fs.Context(P, K.bsk, K.ksk)
+    return K, ctx
+
+
+def test_std_device_keygen_matches_oracle(std):
+    K, _ = std
+    s, S, bsk, ksk = fs.tfhe_keygen(P, K.seed)
+    torch.cuda.synchronize()
+    assert np.array_equal(from_dev(P, s), K.s)
+    assert np.array_equal(from_dev(P, S), K.S)
+    assert np.array_equal(from_dev(P, bsk), K.bsk.ravel())
+    assert np.array_equal(from_dev(P, ksk), K.ksk.ravel())
+
+
+def test_std_bootstrap_batch_4096(std):
+    K, ctx = std
+    B = 4096
+    lwe = si.torus(71, 99, B * (P.n + 1), P.q).reshape(B, P.n + 1)
+    d_lwe = to_dev(P, lwe)
+    out = empty(P, B, P.N + 1)
+    say("mfma bootstrap batch", B)
+    ctx.set_kernel("mfma")
+    ctx.tfhe_bootstrap_batch(d_lwe, out)
+    ks = empty(P, B, P.n + 1)
+    ctx.tfhe_keyswitch_batch(out, ks)
+    say("plain bootstrap batch 24")
+    ctx.set_kernel("plain")
+    out_p = empty(P, 24, P.N + 1)
+    ctx.tfhe_bootstrap_batch(d_lwe[:24].contiguous(), out_p)
+    ctx.set_kernel("mfma")
+    torch.cuda.synchronize()
+    g, gk = from_dev(P, out), from_dev(P, ks)
+    assert np.array_equal(from_dev(P, out_p), g[:24])
+    idx = [0, 1, 15, 16, 2047, 2048, 4080, 4095]
+    tv = oracle.gate_testv(P)
+    say("oracle bootstraps", len(idx))
+    want = oracle.parallel_map(lambda i: oracle.bootstrap(P, K.bsk, lwe[i], tv), idx)
+    for i, w_ in zip(idx, want):
+        assert np.array_equal(g[i], w_), i
+        assert np.array_equal(gk[i], oracle.keyswitch(P, K.ksk, g[i])), i
+
+
+def _enc_table(K, rows, w, seed):
+    col1, col2 = si.table(si.DATA_SEED_BASE + seed, rows, w)
+    c1 = enc_bits(P, K, si.column_bits(col1, w), seed * 10 + 1).reshape(rows, w, P.n + 1)
+    c2 = enc_bits(P, K, si.column_bits(col2, w), seed * 10 + 2).reshape(rows, w, P.n + 1)
+    return col1, col2, c1, c2
+
+
+def test_std_scan_4096_rows(std):
+    """The benchmark's step at full size: every row decrypts to the plaintext
+    truth and sampled rows are bit-exact to the oracle end to end."""
+    K, ctx = std
+    rows, w = 4096, 8
+    col1, col2, c1, c2 = _enc_table(K, rows, w, 2)
+    c_eq, c_lt = int(col1[1234]), 100
+    lit_eq = enc_bits(P, K, [(c_eq >> j) & 1 for j in range(w)], 501)
+    lit_lt = enc_bits(P, K, [(c_lt >> j) & 1 for j in range(w)], 502)
+    d1, d2 = to_dev(P, c1), to_dev(P, c2)
+    m_eq, m_lt = empty(P, rows, P.n + 1), empty(P, rows, P.n + 1)
+    s_eq = empty(P, rows, w, P.n + 1)
+    say("scan eq + select + scan lt over", rows, "rows")
+    ctx.sql_mask_scan(d1, rows, w, "eq", to_dev(P, lit_eq), m_eq)
+    ctx.sql_masked_select(m_eq, d2, rows, w, s_eq)
+    ctx.sql_mask_scan(d1, rows, w, "lt", to_dev(P, lit_lt), m_lt)
+    torch.cuda.synchronize()
+    gm_eq, gm_lt, gs = from_dev(P, m_eq), from_dev(P, m_lt), from_dev(P, s_eq)
+    dec = lambda cts: np.array([oracle.decrypt_bit(P.q, K.s, c) for c in cts.reshape(-1, P.n + 1)])  # noqa: E731
+    assert (dec(gm_eq) == (col1 == c_eq)).all()
+    assert (dec(gm_lt) == (col1 < c_lt)).all()
+    vals = dec(gs).reshape(rows, w)
+    assert [bits_to_int(v) for v in vals] == [int(b) if a == c_eq else 0 for a, b in zip(col1, col2)]
+    # oracle end to end on sampled rows (one matching, one not), level-parallel
+    sample = [1234, 4095]
+    lz = C.LazyBackend(P)
+    roots = []
+    for r in sample:
+        m = C.eq(lz, list(c1[r]), list(lit_eq))
+        roots.append((r, m, C.select(lz, m, list(c2[r]))))
+    mlt = C.lt(lz, list(c1[7]), list(lit_lt))
+    say("oracle end to end on rows", sample, "+ one < chain")
+    C.evaluate(P, K, lz, threads=oracle.default_threads())
+    for r, m, sel in roots:
+        assert np.array_equal(gm_eq[r], C.resolve(P, m)), r
+        assert np.array_equal(gs[r], C.resolve(P, sel)), r
+    assert np.array_equal(gm_lt[7], C.resolve(P, mlt))
