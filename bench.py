@@ -59,6 +59,32 @@ def cpu_baseline(p, threads, per_thread):
                       f"{dt:.1f} s wall"}
 
 
+def kernel_only(p):
+    import torch
+    import seeded_inputs as si
+    import paper_2510_15413_amd as fs
+    s, S, bsk, ksk = fs.tfhe_keygen(p, si.KEY_SEED_BASE + 2)
+    ctx = fs.Context(p, bsk, ksk)
+    B = 4096
+    raw = fs.tfhe_rng_fill(0xB0, 1, B * (p.n + 1) // 2 + 1)
+    lwe = raw.view(torch.int32)[: B * (p.n + 1)].reshape(B, p.n + 1).contiguous()
+    big = torch.empty((B, p.N + 1), dtype=torch.int32, device="cuda")
+    out = torch.empty((B, p.n + 1), dtype=torch.int32, device="cuda")
+    x = torch.ones(64 << 20, dtype=torch.int32, device="cuda")  # 256 MiB
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    ctx.tfhe_bootstrap_batch(lwe, big)
+    ctx.tfhe_keyswitch_batch(big, out)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    n, ms, cts = ctx.timing_read("br")
+    log(f"kernel-only: blind rotation of {B} in {ms:.2f} ms; 256 MiB copy done")
+    print(json.dumps({"mode": "kernel-only", "br_ms": ms, "batch": B,
+                      "achieved_tops": B * int8_ops_per_bootstrap(p) / (ms * 1e-3) / 1e12}))
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +93,9 @@ def main():
     ap.add_argument("--rows", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="profiling mode: one 4096-ciphertext MFMA blind rotation, one key switch and a "
+                         "256 MiB device copy (the counter calibration), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path is single-GPU here.",
@@ -79,6 +108,8 @@ def main():
     from paper_2510_15413_amd import client
 
     p = si.STD
+    if args.kernel_only:
+        return kernel_only(p)
     rows, w = args.rows, 8
     kseed, dseed = si.KEY_SEED_BASE + 2, si.DATA_SEED_BASE + 2
     dev = torch.device("cuda")
