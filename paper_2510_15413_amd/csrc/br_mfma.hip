@@ -50,47 +50,67 @@ FHE_DEV size_t acc_idx(int N, int v, int j, int c) {
 // Gadget digits of the rotate-diff X^{abar} ACC_u - ACC_u for 16 cts, written
 // in the MFMA B-fragment layout: block (u*l+p, chunk) of 1 KB, lane (g,c) holds
 // the 16 digits of coefficients 64*chunk + 16*g + 0..15 of ciphertext c.
-template <typename T, int R>
+// U components starting at u_lo; p_only >= 0 keeps only that level (block 0).
+// The accumulator loads of up to 8 work items per thread are issued together.
+template <typename T, int R, int U>
 FHE_DEV void digits_phase(const T* __restrict__ src, const uint16_t* abar, int n, int i,
-                          int8_t* dbuf, int u_lo, int u_cnt, int p_only, int l, int bgb) {
+                          int8_t* dbuf, int u_lo, int p_only, int l, int bgb) {
     constexpr int N = R * 64;
-    constexpr int Q = Torus<T>::Q;
+    constexpr int ITEMS = CTS * U * (N / 4);
+    constexpr int IPT = (ITEMS + THREADS - 1) / THREADS;
+    constexpr int G = IPT < 4 ? IPT : 4;
     const int lb = l * bgb;
     const uint32_t bgm = (1u << bgb) - 1;
     const int half = 1 << (bgb - 1);
     uint32_t off = 0;
     for (int p = 0; p < l; p++) off += (uint32_t)half << (p * bgb);
-    const int items = CTS * u_cnt * (N / 4);
-    for (int it = threadIdx.x; it < items; it += THREADS) {
-        const int c = it & (CTS - 1);
-        const int rest = it >> 4;
-        const int kg = rest & (N / 4 - 1);
-        const int u = u_lo + rest / (N / 4);
-        const int ab = abar[c * n + i];
-        const T* P = src + (size_t)u * (N / 4) * CTS * 4;
-        auto at = [&](int x) -> T { return P[((size_t)(x >> 2) * CTS + c) * 4 + (x & 3)]; };
-        uint32_t y[4];
+    const int c = threadIdx.x & (CTS - 1);  // fixed per thread (THREADS % 16 == 0)
+    const int ab = abar[c * n + i];
+    const int neg = ab >= N;
+    const int es = neg ? ab - N : ab;
+    for (int k0 = 0; k0 < IPT; k0 += G) {
+        T dv[G][4], rv[G][4];
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const int j = 4 * kg + e;
-            T rot = monomial_coef<T>(at, N, ab, j);
-            T Y = (T)(rot - at(j));
-            y[e] = (uint32_t)round_top<T>(Y, lb) + off;
-        }
-        (void)Q;
-        const int j0 = 4 * kg;
-        const int ch = j0 >> 6, g = (j0 >> 4) & 3, bo = j0 & 15;
-        for (int p = 0; p < l; p++) {
-            if (p_only >= 0 && p != p_only) continue;
-            const int sh = (l - 1 - p) * bgb;
-            uint32_t packed = 0;
+        for (int k = 0; k < G; k++) {
+            const int it = threadIdx.x + (k0 + k) * THREADS;
+            if (ITEMS % THREADS != 0 && it >= ITEMS) continue;
+            const int rest = it >> 4;
+            const int kg = rest & (N / 4 - 1);
+            const int u = u_lo + rest / (N / 4);
+            const T* P = src + (size_t)u * (N / 4) * CTS * 4;
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                int d = (int)((y[e] >> sh) & bgm) - half;
-                packed |= ((uint32_t)(d & 0xFF)) << (8 * e);
+                dv[k][e] = P[((size_t)kg * CTS + c) * 4 + e];
+                const int sidx = 4 * kg + e - es;
+                const int x = sidx >= 0 ? sidx : sidx + N;
+                const T v = P[((size_t)(x >> 2) * CTS + c) * 4 + (x & 3)];
+                rv[k][e] = ((sidx < 0) != (neg != 0)) ? (T)(0 - v) : v;
             }
-            const int blk = p_only >= 0 ? 0 : (u * l + p);
-            *(uint32_t*)(dbuf + ((size_t)blk * R + ch) * 1024 + (g * 16 + c) * 16 + bo) = packed;
+        }
+#pragma unroll
+        for (int k = 0; k < G; k++) {
+            const int it = threadIdx.x + (k0 + k) * THREADS;
+            if (ITEMS % THREADS != 0 && it >= ITEMS) continue;
+            const int rest = it >> 4;
+            const int kg = rest & (N / 4 - 1);
+            const int u = u_lo + rest / (N / 4);
+            uint32_t y[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) y[e] = (uint32_t)round_top<T>((T)(rv[k][e] - dv[k][e]), lb) + off;
+            const int j0 = 4 * kg;
+            const int ch = j0 >> 6, g = (j0 >> 4) & 3, bo = j0 & 15;
+            for (int p = 0; p < l; p++) {
+                if (p_only >= 0 && p != p_only) continue;
+                const int sh = (l - 1 - p) * bgb;
+                uint32_t packed = 0;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int d = (int)((y[e] >> sh) & bgm) - half;
+                    packed |= ((uint32_t)(d & 0xFF)) << (8 * e);
+                }
+                const int blk = p_only >= 0 ? 0 : (u * l + p);
+                *(uint32_t*)(dbuf + ((size_t)blk * R + ch) * 1024 + (g * 16 + c) * 16 + bo) = packed;
+            }
         }
     }
 }
@@ -185,8 +205,10 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     off += (size_t)(DALL ? NB : 1) * R * 1024;
     uint8_t* kbuf = smem + off;
 
-    T* ws0 = (T*)a.ws + (size_t)blockIdx.x * 2 * (2 * N * CTS);
-    T* ws1 = ws0 + 2 * N * CTS;
+    // With all digits of a step formed up front (DALL) the accumulator is
+    // updated in place; otherwise two buffers alternate per step.
+    T* ws0 = (T*)a.ws + (size_t)blockIdx.x * (DALL ? 1 : 2) * (2 * N * CTS);
+    T* ws1 = DALL ? ws0 : ws0 + 2 * N * CTS;
 
     // ---- prologue: modulus switch, accumulator = (0, X^{-bbar} testv)
     for (int idx = tid; idx < CTS * n; idx += THREADS) {
@@ -240,7 +262,7 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     int t = 0;  // linear key-block counter over (i, pass, ub)
     for (int i = 0; i < n; i++) {
         if (DALL) {
-            digits_phase<T, R>(src, abar, n, i, dbuf, 0, 2, -1, l, a.bg_bits);
+            digits_phase<T, R, 2>(src, abar, n, i, dbuf, 0, -1, l, a.bg_bits);
             __syncthreads();
         }
         for (int pass = 0; pass < NPASS; pass++) {
@@ -250,7 +272,7 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
                 for (int e = 0; e < 4; e++) delta[q][e] = 0;
             for (int ub = 0; ub < NB; ub++, t++) {
-                if (!DALL) digits_phase<T, R>(src, abar, n, i, dbuf, ub / l, 1, ub % l, l, a.bg_bits);
+                if (!DALL) digits_phase<T, R, 1>(src, abar, n, i, dbuf, ub / l, ub % l, l, a.bg_bits);
                 if (DOUBLE) {
                     // prefetch the next block of the (i, pass, ub) sequence
                     int ni = i, nub = ub + 1, npass = pass;
@@ -274,15 +296,20 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
                 typedef T vec4 __attribute__((ext_vector_type(4)));
                 const size_t base0 = acc_idx<T>(N, v, 16 * (jr + 4 * pass * RP) + 4 * (lane >> 4), lane & 15);
                 constexpr size_t STEP = (size_t)(64 / 4) * CTS * 4;  // 4 row tiles further
+                // opaque per step, so the 2*RP row addresses are formed here
+                // instead of being hoisted out of the step loop
+                const T* ps = src + base0;
+                T* pd = dst + base0;
+                __asm__ volatile("" : "+v"(ps), "+v"(pd));
                 vec4 cur[RP];
 #pragma unroll
-                for (int q = 0; q < RP; q++) cur[q] = *(const vec4*)(src + base0 + q * STEP);
+                for (int q = 0; q < RP; q++) cur[q] = *(const vec4*)(ps + q * STEP);
 #pragma unroll
                 for (int q = 0; q < RP; q++) {
                     vec4 o;
 #pragma unroll
                     for (int e = 0; e < 4; e++) o[e] = (T)(cur[q][e] + delta[q][e]);
-                    *(vec4*)(dst + base0 + q * STEP) = o;
+                    *(vec4*)(pd + q * STEP) = o;
                 }
             }
         }
