@@ -59,6 +59,26 @@ def cpu_baseline(p, threads, per_thread):
                       f"{dt:.1f} s wall"}
 
 
+def counter_traffic():
+    """HBM bytes per 4096-ciphertext blind-rotation launch from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by what they
+    read for a 256 MiB copy), or None when the kernel source has changed since
+    the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "br_mfma_std_batch4096_counters.json")
+    src = os.path.join(ROOT, "paper_2510_15413_amd", "csrc", "br_mfma.hip")
+    try:
+        with open(path) as f:
+            prof = json.load(f)
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if prof.get("source_sha256_16") != h:
+        return None
+    return prof
+
+
 def kernel_only(p):
     import torch
     import seeded_inputs as si
@@ -185,6 +205,14 @@ def main():
                      "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": None,
                      "kernel": "br_mfma_kernel", "ops_per_bootstrap": ops_bs},
     }
+
+    prof = counter_traffic()
+    if prof is not None:
+        res["roofline"]["traffic"] = round(prof["hbm_bytes_per_launch"])
+        res["roofline"]["traffic_launch"] = "4096-ciphertext launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)"
+        res["roofline"]["algorithmic_bytes_per_launch"] = 4096 * (p.n + 1 + p.N + 1) * 4 + \
+            p.n * 2 * p.l * 2 * 4 * 2 * p.N
+        res["roofline"]["mfma_busy_frac_counter"] = round(prof["mfma_busy_frac"], 4)
 
     if not args.no_plain:
         B = 4096
