@@ -79,6 +79,149 @@ def counter_traffic():
     return prof
 
 
+def batch16(args):
+    """16 tables with log-uniform row counts in [100, 65536] and 16-bit
+    columns, each with one predicate (==, <, BETWEEN) and the masked select of
+    its second column, at the toy parameter set, all tables' gates merged
+    level by level and captured in one HIP graph."""
+    import torch
+    import seeded_inputs as si
+    import paper_2510_15413_amd as fs
+    from paper_2510_15413_amd import client, autotune
+    p = si.TOY
+    w = 16
+    seed = si.DATA_SEED_BASE + 3
+    rows_t, ops_t = si.uneven_tables(seed)
+    s, S, bsk, ksk = fs.tfhe_keygen(p, si.KEY_SEED_BASE + 3)
+    ctx = fs.Context(p, bsk, ksk)
+    del bsk, ksk
+    dev = torch.device("cuda")
+    names = ["eq", "lt", "between"]
+    queries, truths = [], []
+    bs_total = 0
+    for t, (rows, opi) in enumerate(zip(rows_t.tolist(), ops_t.tolist())):
+        op = names[opi]
+        col1, col2 = si.table(seed, rows, w, table_id=t)
+        lits = si.uniform_ints(seed, si.TAG_LITERAL | (t << 32), 3, w)
+        if op == "eq":
+            a, b = int(col1[int(lits[0]) % rows]), None
+        elif op == "lt":
+            a, b = int(lits[1]), None
+        else:
+            a, b = sorted((int(lits[1]), int(lits[2])))
+        enc = lambda vals, tag: client.encrypt_bits(  # noqa: E731
+            p, seed, s, client.value_bits(torch.as_tensor(vals, dtype=torch.int64, device=dev), w), tag_hi=tag)
+        q = dict(col=enc(col1.astype("int64"), 100 + 4 * t), sel_col=enc(col2.astype("int64"), 101 + 4 * t),
+                 rows=rows, w=w, op=op, lit_a=enc([a], 102 + 4 * t)[0],
+                 lit_b=enc([b], 103 + 4 * t)[0] if b is not None else None,
+                 mask=torch.empty((rows, p.n + 1), dtype=torch.int32, device=dev),
+                 sel_out=torch.empty((rows, w, p.n + 1), dtype=torch.int32, device=dev))
+        queries.append(q)
+        truth = (col1 == a) if op == "eq" else (col1 < a) if op == "lt" else ((col1 >= a) & (col1 <= b))
+        truths.append(truth)
+        bs_total += rows * ({"eq": 2 * w - 1, "lt": w, "between": 2 * w + 1}[op] + w)
+    torch.cuda.synchronize()
+    log(f"batch16: {int(rows_t.sum())} rows in 16 tables, {bs_total} bootstraps per run")
+
+    def run():
+        ctx.sql_scan_batch(queries, use_graph=True)
+        torch.cuda.synchronize()
+
+    tuned = None
+    if args.autotune:
+        tuned, _ = autotune.tune(ctx, f"batch16-{bs_total}", run, cache_path=None, log=log)
+    for _ in range(args.warmup):
+        run()
+    ctx.timing_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        run()
+        log(f"batch16 run {i + 1}/{args.steps}: {time.perf_counter() - t0:.2f} s")
+    wall = time.perf_counter() - t0
+    # the graph's kernels are not event-timed; time one ungraphed run for the kernel split
+    ctx.sql_scan_batch(queries, use_graph=False)
+    torch.cuda.synchronize()
+    br_n, br_ms, br_cts = ctx.timing_read("br")
+    ctx.timing_enable(False)
+    ok = all(bool((client.decrypt_bits(p, s, q["mask"]).cpu().numpy() == tr).all()) for q, tr in zip(queries, truths))
+    ops_bs = int8_ops_per_bootstrap(p)
+    ach = br_cts * ops_bs / (br_ms * 1e-3) / 1e12 if br_ms > 0 else 0.0
+    res = {"workload": "batch16", "params": "toy n=64 N=256 l=2 Bg=2^8", "tables": len(queries),
+           "rows": int(rows_t.sum()), "rows_per_table": rows_t.tolist(), "ops": [names[o] for o in ops_t.tolist()],
+           "bootstraps_per_run": bs_total, "runs": args.steps, "seconds_per_run": round(wall / args.steps, 4),
+           "bootstraps_per_s": round(bs_total * args.steps / wall, 1),
+           "rows_per_s": round(int(rows_t.sum()) * args.steps / wall, 1), "hipgraph": True,
+           "tuning": tuned, "decrypt_ok": ok,
+           "ungraphed_kernel_split": {"br_launches": br_n, "br_ms": round(br_ms, 2),
+                                      "br_achieved_int8_tops": round(ach, 1)}}
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+def serve(args):
+    """Open-loop Poisson arrivals of SELECT SUM(col2) WHERE col1 op c over a
+    prefix of one resident table (toy parameters, 8-bit columns), prefix
+    lengths log-uniform in [1e3, max_rows], op uniform over {==, <, >}."""
+    import torch
+    import seeded_inputs as si
+    import paper_2510_15413_amd as fs
+    from paper_2510_15413_amd import client, serve as srv
+    p = si.TOY
+    w = 8
+    seed = si.DATA_SEED_BASE + 5
+    s, S, bsk, ksk = fs.tfhe_keygen(p, si.KEY_SEED_BASE + 5)
+    ctx = fs.Context(p, bsk, ksk)
+    del bsk, ksk
+    dev = torch.device("cuda")
+    R = args.max_rows
+    col1, col2 = si.table(seed, R, w)
+    t1 = torch.from_numpy(col1.astype("int64")).to(dev)
+    t2 = torch.from_numpy(col2.astype("int64")).to(dev)
+    c1 = torch.empty((R, w, p.n + 1), dtype=torch.int32, device=dev)
+    c2 = torch.empty_like(c1)
+    step = 1 << 16
+    for r0 in range(0, R, step):  # encrypt in slices to bound temporaries
+        r1 = min(R, r0 + step)
+        c1[r0:r1] = client.encrypt_bits(p, seed, s, client.value_bits(t1[r0:r1], w), tag_hi=1, start=r0 * w)
+        c2[r0:r1] = client.encrypt_bits(p, seed, s, client.value_bits(t2[r0:r1], w), tag_hi=2, start=r0 * w)
+    torch.cuda.synchronize()
+    log(f"serve: table of {R} rows encrypted")
+    free, total = torch.cuda.mem_get_info()
+    budget = int(free * 0.8) + (total - free) // 8
+    results = []
+    names = ["eq", "lt", "gt"]
+    for li, lam in enumerate(float(x) for x in args.rates.split(",")):
+        n = args.queries
+        rows = si.log_uniform_int(seed + li, si.TAG_SHAPE, n, 1000, R).clip(1, R)
+        ops = (si.uniform_ints(seed + li, si.TAG_SHAPE, n, 16, start=n) % 3).astype("int64")
+        lits = si.uniform_ints(seed + li, si.TAG_LITERAL, n, w)
+        arrivals = srv.poisson_arrivals(seed + li, n, lam)
+        qs = []
+        for i in range(n):
+            op = names[int(ops[i])]
+            lit = int(col1[int(lits[i]) % int(rows[i])]) if op == "eq" else int(lits[i])
+            lt = client.encrypt_bits(p, seed, s, client.value_bits(torch.tensor([lit], device=dev), w)[0],
+                                     tag_hi=1000 + 100 * li + i)
+            qs.append(dict(col=c1, sum_col=c2, rows=int(rows[i]), w=w, op=op, lit_a=lt, lit=lit,
+                           out=torch.empty((srv.sum_bits(w, int(rows[i])), p.n + 1), dtype=torch.int32,
+                                           device=dev)))
+        recs, stats = srv.run(ctx, qs, arrivals, budget, log=log)
+        ok = True
+        for q in qs:
+            r = q["rows"]
+            pred = {"eq": col1[:r] == q["lit"], "lt": col1[:r] < q["lit"], "gt": col1[:r] > q["lit"]}[q["op"]]
+            got = int(client.bits_to_values(client.decrypt_bits(p, s, q["out"])[None, :]).item())
+            ok &= got == int((col2[:r].astype("int64") * pred).sum())
+        summ = srv.summarize(recs, stats)
+        summ.update({"lambda": lam, "decrypt_ok": bool(ok), "mean_rows": float(rows.mean())})
+        results.append(summ)
+        log(f"serve lambda={lam}: p50 {summ['p50_s']:.2f} s p99 {summ['p99_s']:.2f} s "
+            f"{summ['rows_per_s']:.0f} rows/s ok={ok}")
+    ctx.close()
+    print(json.dumps({"workload": "serve", "params": "toy n=64 N=256 l=2 Bg=2^8", "bits": w,
+                      "table_rows": R, "hbm_budget_bytes": budget, "rates": results}), flush=True)
+
+
 def kernel_only(p):
     import torch
     import seeded_inputs as si
@@ -113,6 +256,13 @@ def main():
     ap.add_argument("--rows", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
+    ap.add_argument("--workload", default="std", choices=["std", "batch16", "serve"],
+                    help="std: the headline 4096-row scan; batch16: 16 uneven tables at toy "
+                         "parameters in one level-batched hipGraph schedule")
+    ap.add_argument("--autotune", action="store_true", help="batch16: tune the executor knobs first")
+    ap.add_argument("--rates", default="1,2,4,8,16,32,64", help="serve: Poisson rates (queries/s)")
+    ap.add_argument("--queries", type=int, default=16, help="serve: queries per rate")
+    ap.add_argument("--max-rows", type=int, default=1 << 20, help="serve: largest table prefix")
     ap.add_argument("--kernel-only", action="store_true",
                     help="profiling mode: one 4096-ciphertext MFMA blind rotation, one key switch and a "
                          "256 MiB device copy (the counter calibration), then exit")
@@ -130,6 +280,10 @@ def main():
     p = si.STD
     if args.kernel_only:
         return kernel_only(p)
+    if args.workload == "batch16":
+        return batch16(args)
+    if args.workload == "serve":
+        return serve(args)
     rows, w = args.rows, 8
     kseed, dseed = si.KEY_SEED_BASE + 2, si.DATA_SEED_BASE + 2
     dev = torch.device("cuda")

@@ -94,6 +94,17 @@ void tfhe_ctx_destroy(tfhe_ctx* ctx);
 const char* tfhe_last_error(const tfhe_ctx* ctx);
 /* Select TFHE_KERNEL_MFMA or TFHE_KERNEL_PLAIN for later blind rotations. */
 int tfhe_set_kernel(tfhe_ctx* ctx, int kind);
+/* Tuning knobs (none changes an output bit):
+ *   TFHE_TUNE_MAX_BATCH  maximum ciphertexts per blind-rotation launch when a
+ *                        circuit level is split into launches (default 65536);
+ *   TFHE_TUNE_ROW_PASS   MFMA kernel row tiles per pass (0 = default for N,
+ *                        otherwise one of the instantiated variants, e.g. N/64
+ *                        or N/128 for q = 32).
+ * Returns TFHE_EINVAL for an unknown key or unsupported value. */
+#define TFHE_TUNE_MAX_BATCH 1
+#define TFHE_TUNE_ROW_PASS 2
+int tfhe_set_tuning(tfhe_ctx* ctx, int key, int64_t value);
+
 /* Waits for the stream and reports any asynchronous fault. */
 int tfhe_ctx_sync(tfhe_ctx* ctx, void* hip_stream);
 
@@ -162,6 +173,47 @@ int sql_scan_batch(tfhe_ctx* ctx, const sql_table_query* q, uint32_t count, int 
 int tfhe_timing_enable(tfhe_ctx* ctx, int on);
 int tfhe_timing_read(tfhe_ctx* ctx, int kind, uint64_t* launches, double* total_ms,
                      uint64_t* cts);
+
+/* ---- continuous-batching query server ----
+ * Serves SELECT SUM(col2) WHERE col1 op literal queries (Algorithm 2's mask,
+ * the If-Then-Else of Eqs. 2-3 and the aggregation after Eq. 3).  Queries
+ * are admitted while the device memory they need (circuit temporaries) fits
+ * in the budget next to the resident keys and the server's staging buffers;
+ * each tick runs the next circuit level of every active query -- up to
+ * max_batch gates, a level may span ticks -- as one batched combine / blind
+ * rotation / key switch, so queries that arrive while others run share the
+ * same launches.  A query's result bits do not depend on what it is batched
+ * with. */
+typedef struct sql_server sql_server;
+
+typedef struct sql_sum_query {
+    const void* d_col;      /* [rows][w][n+1] predicate column */
+    const void* d_sum_col;  /* [rows][w][n+1] summed column */
+    uint32_t rows;
+    uint32_t w;
+    int op;                 /* SQL_OP_EQ, SQL_OP_LT, SQL_OP_GT or SQL_OP_BETWEEN */
+    const void* d_lit_a;    /* [w][n+1] */
+    const void* d_lit_b;    /* [w][n+1] for BETWEEN, else NULL */
+    void* d_sum;            /* [w + ceil(log2 rows)][n+1] result */
+} sql_sum_query;
+
+/* hbm_budget_bytes: total device memory the server may account for (keys,
+ * staging, temporaries); max_batch: gates per tick. */
+int sql_server_create(tfhe_ctx* ctx, size_t hbm_budget_bytes, uint32_t max_batch,
+                      sql_server** out);
+void sql_server_destroy(sql_server* srv);
+/* Queue a query; its buffers must stay valid until it is done.  *id receives
+ * its identifier.  Fails with TFHE_ENOMEM if it could never fit the budget. */
+int sql_server_submit(sql_server* srv, const sql_sum_query* q, uint64_t* id);
+/* One tick on the stream (blocks until its kernels finish).  Outputs (any may
+ * be NULL): gates run, active and queued query counts after the tick. */
+int sql_server_step(sql_server* srv, void* hip_stream, uint32_t* gates, uint32_t* active,
+                    uint32_t* queued);
+/* 1 when query id has completed (its d_sum holds the result), 0 otherwise,
+ * negative for an unknown id. */
+int sql_server_done(sql_server* srv, uint64_t id);
+/* Device bytes the server currently accounts for. */
+size_t sql_server_bytes_in_use(const sql_server* srv);
 
 /* ---- client-side helpers on the device (synthetic data and checks) ---- */
 

@@ -6,5 +6,5 @@ hot path of FHE-SQL's oblivious selection on one GPU: TFHE gate bootstrapping
 extraction, key switching) inside the boolean circuits of the WHERE mask, the
 masked select and the masked SUM.  This package is its thin Python binding.
 """
-from ._lib import (Context, FheError, load, tfhe_keygen, tfhe_lwe_encrypt, tfhe_lwe_phase,  # noqa: F401
+from ._lib import (Context, Server, FheError, load, tfhe_keygen, tfhe_lwe_encrypt, tfhe_lwe_phase,  # noqa: F401
                    tfhe_rng_fill, sum_width, SQL_OPS, GATE_OPS, LIB_PATH)

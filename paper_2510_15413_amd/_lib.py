@@ -32,7 +32,11 @@ EXPORTS = [
     "tfhe_keyswitch_batch", "tfhe_gate_batch", "sql_mask_scan", "sql_masked_select",
     "sql_masked_sum", "sql_scan_batch", "tfhe_rng_fill", "tfhe_keygen",
     "tfhe_lwe_encrypt", "tfhe_lwe_phase", "tfhe_timing_enable", "tfhe_timing_read",
+    "tfhe_set_tuning", "sql_server_create", "sql_server_destroy", "sql_server_submit",
+    "sql_server_step", "sql_server_done", "sql_server_bytes_in_use",
 ]
+TFHE_TUNE_MAX_BATCH = 1
+TFHE_TUNE_ROW_PASS = 2
 
 
 class FheError(RuntimeError):
@@ -43,6 +47,12 @@ class TfheParams(ctypes.Structure):
     _fields_ = [("torus_bits", ctypes.c_uint32), ("n", ctypes.c_uint32), ("k", ctypes.c_uint32),
                 ("N", ctypes.c_uint32), ("bg_bits", ctypes.c_uint32), ("l", ctypes.c_uint32),
                 ("ks_base_bits", ctypes.c_uint32), ("ks_t", ctypes.c_uint32)]
+
+
+class SqlSumQuery(ctypes.Structure):
+    _fields_ = [("d_col", ctypes.c_void_p), ("d_sum_col", ctypes.c_void_p), ("rows", ctypes.c_uint32),
+                ("w", ctypes.c_uint32), ("op", ctypes.c_int), ("d_lit_a", ctypes.c_void_p),
+                ("d_lit_b", ctypes.c_void_p), ("d_sum", ctypes.c_void_p)]
 
 
 class SqlTableQuery(ctypes.Structure):
@@ -84,6 +94,13 @@ def load():
         "tfhe_lwe_encrypt": (i32, [P, u64, u64, u64, u32, u64, vp, vp, vp, u64, u32, vp]),
         "tfhe_lwe_phase": (i32, [P, vp, vp, vp, u64, u32, vp]),
         "tfhe_timing_enable": (i32, [vp, i32]),
+        "tfhe_set_tuning": (i32, [vp, i32, ctypes.c_int64]),
+        "sql_server_create": (i32, [vp, sz, u32, ctypes.POINTER(vp)]),
+        "sql_server_destroy": (None, [vp]),
+        "sql_server_submit": (i32, [vp, ctypes.POINTER(SqlSumQuery), ctypes.POINTER(u64)]),
+        "sql_server_step": (i32, [vp, vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]),
+        "sql_server_done": (i32, [vp, u64]),
+        "sql_server_bytes_in_use": (sz, [vp]),
         "tfhe_timing_read": (i32, [vp, i32, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(u64)]),
     }
@@ -180,6 +197,13 @@ class Context:
                                          ctypes.byref(cts)), "tfhe_timing_read")
         return n.value, ms.value, cts.value
 
+    def set_tuning(self, max_batch=None, row_pass=None):
+        L = load()
+        if max_batch is not None:
+            self._rc(L.tfhe_set_tuning(self._h, TFHE_TUNE_MAX_BATCH, int(max_batch)), "tfhe_set_tuning")
+        if row_pass is not None:
+            self._rc(L.tfhe_set_tuning(self._h, TFHE_TUNE_ROW_PASS, int(row_pass)), "tfhe_set_tuning")
+
     # -- evaluation -------------------------------------------------------
     def set_kernel(self, kind):
         self._rc(load().tfhe_set_kernel(self._h, TFHE_KERNEL_PLAIN if kind == "plain" else TFHE_KERNEL_MFMA),
@@ -239,6 +263,57 @@ class Context:
                                    q["sel_out"].data_ptr() if q.get("sel_out") is not None else None)
         self._rc(load().sql_scan_batch(self._h, arr, len(queries), 1 if use_graph else 0, _stream(stream)),
                  "sql_scan_batch")
+
+
+class Server:
+    """Continuous-batching query server (sql_server_*) on a context."""
+
+    def __init__(self, ctx, hbm_budget_bytes, max_batch=65536):
+        self.ctx = ctx
+        self._h = ctypes.c_void_p()
+        rc = load().sql_server_create(ctx._h, int(hbm_budget_bytes), int(max_batch), ctypes.byref(self._h))
+        ctx._rc(rc, "sql_server_create")
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().sql_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, col, sum_col, rows, w, op, lit_a, out, lit_b=None):
+        """Queue SELECT SUM(sum_col) WHERE col op lit; returns the query id."""
+        for t, nm in ((col, "col"), (sum_col, "sum_col"), (lit_a, "lit_a"), (lit_b, "lit_b"), (out, "out")):
+            _check_dev(t, nm)
+        q = SqlSumQuery(col.data_ptr(), sum_col.data_ptr(), rows, w, SQL_OPS.get(op, op), lit_a.data_ptr(),
+                        lit_b.data_ptr() if lit_b is not None else None, out.data_ptr())
+        qid = ctypes.c_uint64()
+        self.ctx._rc(load().sql_server_submit(self._h, ctypes.byref(q), ctypes.byref(qid)), "sql_server_submit")
+        self._keep[qid.value] = (col, sum_col, lit_a, lit_b, out)
+        return qid.value
+
+    def step(self, stream=None):
+        """One tick; returns (gates run, active, queued)."""
+        g, a, q = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        self.ctx._rc(load().sql_server_step(self._h, _stream(stream), ctypes.byref(g), ctypes.byref(a),
+                                            ctypes.byref(q)), "sql_server_step")
+        return g.value, a.value, q.value
+
+    def done(self, qid):
+        rc = load().sql_server_done(self._h, qid)
+        if rc < 0:
+            raise FheError(f"unknown query id {qid}")
+        if rc == 1:
+            self._keep.pop(qid, None)
+        return rc == 1
+
+    def bytes_in_use(self):
+        return load().sql_server_bytes_in_use(self._h)
 
 
 def sum_width(w, rows):

@@ -369,6 +369,19 @@ int dispatch_dall(tfhe_ctx* c, const BrArgs& a, hipStream_t s) {
 
 }  // namespace
 
+// Row tiles per pass instantiated for each (q, N); the first is the default.
+bool mfma_row_pass_supported(const tfhe_ctx* c, int rp) {
+    const int N = (int)c->p.N;
+    if (c->q == 32) {
+        if (N == 256) return rp == 4 || rp == 2;
+        if (N == 512) return rp == 8 || rp == 4;
+        if (N == 1024) return rp == 16 || rp == 8;
+        return false;
+    }
+    if (N == 2048) return rp == 4 || rp == 8;
+    return false;
+}
+
 size_t mfma_ws_bytes(const tfhe_ctx* c, uint32_t B) {
     const size_t grid = (B + CTS - 1) / CTS;
     return grid * 2 * 2 * (size_t)c->p.N * CTS * word_bytes(c);
@@ -388,12 +401,13 @@ int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_
     a.l = (int)c->p.l;
     a.bg_bits = (int)c->p.bg_bits;
     const int N = (int)c->p.N;
+    const int rp = c->row_pass;
     if (c->q == 32) {
         switch (N) {
             case 64: return dispatch_dall<uint32_t, 1, 1>(c, a, s);
-            case 256: return dispatch_dall<uint32_t, 4, 4>(c, a, s);
-            case 512: return dispatch_dall<uint32_t, 8, 8>(c, a, s);
-            case 1024: return dispatch_dall<uint32_t, 16, 16>(c, a, s);
+            case 256: return rp == 2 ? dispatch_dall<uint32_t, 4, 2>(c, a, s) : dispatch_dall<uint32_t, 4, 4>(c, a, s);
+            case 512: return rp == 4 ? dispatch_dall<uint32_t, 8, 4>(c, a, s) : dispatch_dall<uint32_t, 8, 8>(c, a, s);
+            case 1024: return rp == 8 ? dispatch_dall<uint32_t, 16, 8>(c, a, s) : dispatch_dall<uint32_t, 16, 16>(c, a, s);
             case 2048: return dispatch_dall<uint32_t, 32, 8>(c, a, s);
         }
     } else {
@@ -402,7 +416,7 @@ int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_
             case 256: return dispatch_dall<uint64_t, 4, 4>(c, a, s);
             case 512: return dispatch_dall<uint64_t, 8, 4>(c, a, s);
             case 1024: return dispatch_dall<uint64_t, 16, 4>(c, a, s);
-            case 2048: return dispatch_dall<uint64_t, 32, 4>(c, a, s);
+            case 2048: return rp == 8 ? dispatch_dall<uint64_t, 32, 8>(c, a, s) : dispatch_dall<uint64_t, 32, 4>(c, a, s);
         }
     }
     return ctx_fail(c, TFHE_EINVAL, "unsupported N for the MFMA kernel");

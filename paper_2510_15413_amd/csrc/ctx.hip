@@ -188,6 +188,24 @@ extern "C" int tfhe_set_kernel(tfhe_ctx* c, int kind) {
     return TFHE_OK;
 }
 
+bool mfma_row_pass_supported(const tfhe_ctx* c, int rp);
+
+extern "C" int tfhe_set_tuning(tfhe_ctx* c, int key, int64_t value) {
+    if (!c) return TFHE_EINVAL;
+    if (key == TFHE_TUNE_MAX_BATCH) {
+        if (value < 16 || value > (1 << 22)) return ctx_fail(c, TFHE_EINVAL, "max batch must be in [16, 2^22]");
+        c->max_batch = (uint32_t)value;
+        return TFHE_OK;
+    }
+    if (key == TFHE_TUNE_ROW_PASS) {
+        if (value != 0 && !mfma_row_pass_supported(c, (int)value))
+            return ctx_fail(c, TFHE_EINVAL, "row tiles per pass not instantiated for this N");
+        c->row_pass = (int)value;
+        return TFHE_OK;
+    }
+    return ctx_fail(c, TFHE_EINVAL, "unknown tuning key");
+}
+
 extern "C" int tfhe_ctx_sync(tfhe_ctx* c, void* stream) {
     if (!c) return TFHE_EINVAL;
     return hip_check(c, hipStreamSynchronize((hipStream_t)stream), "stream synchronize");

@@ -130,6 +130,8 @@ struct tfhe_ctx {
     tfhe_params p{};
     int q = 32;
     int kernel = TFHE_KERNEL_MFMA;
+    uint32_t max_batch = 65536;  // ciphertexts per blind-rotation launch in circuits
+    int row_pass = 0;            // MFMA row tiles per pass (0 = default)
     void* d_bsk = nullptr;     // [n][(k+1)l][k+1][N] words
     int8_t* d_bsk8 = nullptr;  // [n][(k+1)l][k+1][LIMBS][2N] Toeplitz limb form
     void* d_ksk = nullptr;     // [kN][t][2^b][n+1] words

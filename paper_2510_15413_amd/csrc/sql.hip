@@ -234,6 +234,60 @@ struct Builder {
         }
         return lev + 1;
     }
+
+    // Masked SUM: select into a [rows][w] operand buffer, then a pairwise
+    // ripple-carry adder tree over rows (pairs (0,1),(2,3),...; an odd last
+    // operand passes up unchanged with a trivial FALSE top bit).  Result bits
+    // (w + ceil(log2 rows) of them) go to `sum` (stride n+1 words per bit).
+    size_t masked_sum(size_t lev, uint32_t rows, uint32_t w, const Ref& mask, const Ref& col, uint64_t sum,
+                      uint64_t false_ct) {
+        Ref cur = tmp(rows * w);
+        cur.stride = (int64_t)(w * lw);
+        lev = select(lev, rows, w, mask, col, cur);
+        uint32_t cnt = rows, width = w;
+        auto at = [&](const Ref& base, uint32_t op, uint32_t j, int64_t stride) -> Ref {
+            return Ref{base.addr + ((uint64_t)op * base.stride + (uint64_t)j * lw) * wb, stride};
+        };
+        while (cnt > 1) {
+            const uint32_t pairs = cnt / 2;
+            const bool odd = cnt & 1;
+            const uint32_t nw = width + 1;
+            const bool last = (pairs + (odd ? 1 : 0)) == 1;
+            Ref res;
+            if (last) res = Ref{sum, (int64_t)(nw * lw)};
+            else { res = tmp((pairs + (odd ? 1 : 0)) * nw); res.stride = (int64_t)(nw * lw); }
+            const int64_t xs = 2 * cur.stride;  // operand-pair stride
+            Ref x0 = at(cur, 0, 0, xs), y0 = at(cur, 1, 0, xs);
+            Ref carry = width == 1 ? at(res, 0, 1, res.stride) : tmp(pairs);
+            gate(lev, G_XOR, pairs, {&x0, &y0}, at(res, 0, 0, res.stride));
+            gate(lev, G_AND, pairs, {&x0, &y0}, carry);
+            Ref tb = tmp(pairs * width);
+            tb.stride = (int64_t)(width * lw);
+            for (uint32_t j = 1; j < width; j++) {
+                Ref xj = at(cur, 0, j, xs), yj = at(cur, 1, j, xs);
+                gate(lev, G_XOR, pairs, {&xj, &yj}, at(tb, 0, j, tb.stride));
+            }
+            for (uint32_t j = 1; j < width; j++) {
+                Ref xj = at(cur, 0, j, xs), yj = at(cur, 1, j, xs);
+                Ref tj = at(tb, 0, j, tb.stride);
+                Ref nc = j + 1 == width ? at(res, 0, width, res.stride) : tmp(pairs);
+                gate(lev + j, G_XOR, pairs, {&tj, &carry}, at(res, 0, j, res.stride));
+                gate(lev + j, G_MAJ, pairs, {&xj, &yj, &carry}, nc);
+                carry = nc;
+            }
+            if (odd) {
+                const Ref src = at(cur, cnt - 1, 0, 0), dst = at(res, pairs, 0, 0);
+                copy_push(lev, src.addr, dst.addr, (uint64_t)width * lw * wb);
+                copy_push(lev, false_ct, at(res, pairs, width, 0).addr, lw * wb);
+            }
+            lev += width;
+            cnt = pairs + (odd ? 1 : 0);
+            width = nw;
+            cur = res;
+        }
+        if (rows == 1) copy_push(lev, cur.addr, sum, (uint64_t)w * lw * wb);
+        return lev + (rows == 1 ? 1 : 0);
+    }
 };
 
 // ---------------------------------------------------------- execution
@@ -245,7 +299,7 @@ struct Exec {
     uint32_t max_batch;
 
     Exec(tfhe_ctx* cc, hipStream_t ss) : c(cc), s(ss), wb(word_bytes(cc)), lw(cc->p.n + 1),
-                                          bw((size_t)cc->p.k * cc->p.N + 1), max_batch(65536) {}
+                                          bw((size_t)cc->p.k * cc->p.N + 1), max_batch(cc->max_batch) {}
 
     // Lay out the workspace: temporaries, then per-level staging.
     int run(Netlist& net, bool use_graph) {
@@ -448,62 +502,237 @@ extern "C" int sql_masked_sum(tfhe_ctx* c, const void* d_mask, const void* d_col
     if (!d_mask || !d_col || !d_sum) return ctx_fail(c, TFHE_EINVAL, "null ciphertext pointer");
     if (w < 1 || w > 32) return ctx_fail(c, TFHE_ESHAPE, "column width must be 1..32 bits");
     if (!rows) return ctx_fail(c, TFHE_ESHAPE, "SUM needs at least one row");
-    Builder b(c);
-    const size_t lw = b.lw, wb = b.wb;
-    uint32_t width = w;
     uint32_t final_w = w;
     for (uint32_t r = rows; r > 1; r = (r + 1) / 2) final_w++;
     if (width_out) *width_out = final_w;
-    // level 0: masked select into a [rows][w] operand buffer
-    Ref cur = b.tmp(rows * w);
-    cur.stride = (int64_t)(w * lw);
-    size_t lev = b.select(0, rows, w, dev(d_mask, lw), dev(d_col, (size_t)w * lw), cur);
-    uint32_t cnt = rows;
-    auto at = [&](const Ref& base, uint32_t op, uint32_t j, int64_t stride) -> Ref {
-        return Ref{base.addr + ((uint64_t)op * base.stride + (uint64_t)j * lw) * wb, stride};
-    };
-    while (cnt > 1) {
-        const uint32_t pairs = cnt / 2;
-        const bool odd = cnt & 1;
-        const uint32_t nw = width + 1;
-        const bool last = (pairs + (odd ? 1 : 0)) == 1;
-        Ref res;
-        if (last) res = Ref{(uint64_t)(uintptr_t)d_sum, (int64_t)(nw * lw)};
-        else { res = b.tmp((pairs + (odd ? 1 : 0)) * nw); res.stride = (int64_t)(nw * lw); }
-        const int64_t xs = 2 * cur.stride;  // pair stride
-        Ref x0 = at(cur, 0, 0, xs), y0 = at(cur, 1, 0, xs);
-        Ref carry = width == 1 ? at(res, 0, 1, res.stride) : b.tmp(pairs);
-        b.gate(lev, G_XOR, pairs, {&x0, &y0}, at(res, 0, 0, res.stride));
-        b.gate(lev, G_AND, pairs, {&x0, &y0}, carry);
-        Ref tb = b.tmp(pairs * width);
-        tb.stride = (int64_t)(width * lw);
-        for (uint32_t j = 1; j < width; j++) {
-            Ref xj = at(cur, 0, j, xs), yj = at(cur, 1, j, xs);
-            b.gate(lev, G_XOR, pairs, {&xj, &yj}, at(tb, 0, j, tb.stride));
-        }
-        for (uint32_t j = 1; j < width; j++) {
-            Ref xj = at(cur, 0, j, xs), yj = at(cur, 1, j, xs);
-            Ref tj = at(tb, 0, j, tb.stride);
-            Ref nc = j + 1 == width ? at(res, 0, width, res.stride) : b.tmp(pairs);
-            b.gate(lev + j, G_XOR, pairs, {&tj, &carry}, at(res, 0, j, res.stride));
-            b.gate(lev + j, G_MAJ, pairs, {&xj, &yj, &carry}, nc);
-            carry = nc;
-        }
-        if (odd) {
-            // the last operand passes up unchanged, zero-extended by a trivial FALSE
-            const Ref src = at(cur, cnt - 1, 0, 0), dst = at(res, pairs, 0, 0);
-            b.copy_push(lev, src.addr, dst.addr, (uint64_t)width * lw * wb);
-            b.copy_push(lev, (uint64_t)(uintptr_t)c->d_false, at(res, pairs, width, 0).addr, lw * wb);
-        }
-        lev += width;
-        cnt = pairs + (odd ? 1 : 0);
-        width = nw;
-        cur = res;
-    }
-    if (rows == 1) {
-        // a single row: the sum is the selected value itself
-        b.copy_push(lev, cur.addr, (uint64_t)(uintptr_t)d_sum, (uint64_t)w * lw * wb);
-    }
+    Builder b(c);
+    const size_t lw = b.lw;
+    b.masked_sum(0, rows, w, dev(d_mask, lw), dev(d_col, (size_t)w * lw), (uint64_t)(uintptr_t)d_sum,
+                 (uint64_t)(uintptr_t)c->d_false);
     Exec ex(c, (hipStream_t)stream);
     return ex.run(b.net, false);
+}
+
+// ------------------------------------------------- continuous-batching server
+
+#include <deque>
+#include <unordered_set>
+
+namespace {
+
+struct ServerQuery {
+    uint64_t id = 0;
+    Netlist net;
+    size_t tmp_bytes = 0;
+    void* tmp = nullptr;
+    size_t level = 0;   // next level to run
+    size_t seg = 0;     // next segment of that level
+    uint32_t row = 0;   // rows of that segment already run
+    bool copies_done = false;
+};
+
+constexpr uint32_t kMaxActive = 256;
+constexpr size_t kSegCap = 1 << 15;
+
+}  // namespace
+
+struct sql_server {
+    tfhe_ctx* c = nullptr;
+    size_t budget = 0, fixed = 0, in_use = 0;
+    uint32_t max_batch = 0;
+    uint64_t next_id = 1;
+    std::deque<ServerQuery*> queue;
+    std::vector<ServerQuery*> active;
+    std::unordered_set<uint64_t> done, known;
+    void* stage = nullptr;
+    uint8_t *lwe = nullptr, *big = nullptr, *brws = nullptr;
+    uint64_t* ptrs = nullptr;
+    int32_t* tvi = nullptr;
+    Segment* dsegs = nullptr;
+    uint32_t* dstart = nullptr;
+    Segment* hsegs = nullptr;
+    uint32_t* hstart = nullptr;
+};
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" int sql_server_create(tfhe_ctx* c, size_t budget, uint32_t max_batch, sql_server** out) {
+    if (!c || !out || max_batch < 16) return TFHE_EINVAL;
+    *out = nullptr;
+    sql_server* sv = new sql_server();
+    sv->c = c;
+    sv->budget = budget;
+    sv->max_batch = max_batch;
+    const size_t wb = word_bytes(c), lw = c->p.n + 1, bw = (size_t)c->p.k * c->p.N + 1;
+    const size_t NL = c->q == 32 ? 4 : 8;
+    const size_t keys = (tfhe_bsk_words(&c->p) + tfhe_ksk_words(&c->p)) * wb +
+                        (size_t)c->p.n * 2 * c->p.l * 2 * NL * 2 * c->p.N;
+    const size_t lwe_b = al256((size_t)max_batch * lw * wb), big_b = al256((size_t)max_batch * bw * wb);
+    const size_t ptr_b = al256((size_t)max_batch * 8), tvi_b = al256((size_t)max_batch * 4);
+    const size_t br_b = al256(blind_rotate_ws_bytes(c, max_batch));
+    const size_t seg_b = al256(kSegCap * sizeof(Segment)), st_b = al256(kSegCap * 4);
+    const size_t stage_b = lwe_b + big_b + ptr_b + tvi_b + br_b + seg_b + st_b;
+    sv->fixed = keys + stage_b;
+    if (sv->fixed > budget) {
+        delete sv;
+        return ctx_fail(c, TFHE_ENOMEM, "HBM budget smaller than keys + server staging");
+    }
+    int rc = hip_check(c, hipMalloc(&sv->stage, stage_b), "server staging");
+    if (!rc) rc = hip_check(c, hipHostMalloc((void**)&sv->hsegs, kSegCap * sizeof(Segment)), "server pinned segments");
+    if (!rc) rc = hip_check(c, hipHostMalloc((void**)&sv->hstart, kSegCap * 4), "server pinned starts");
+    if (rc) {
+        sql_server_destroy(sv);
+        return rc;
+    }
+    uint8_t* p = (uint8_t*)sv->stage;
+    sv->lwe = p; p += lwe_b;
+    sv->big = p; p += big_b;
+    sv->ptrs = (uint64_t*)p; p += ptr_b;
+    sv->tvi = (int32_t*)p; p += tvi_b;
+    sv->brws = p; p += br_b;
+    sv->dsegs = (Segment*)p; p += seg_b;
+    sv->dstart = (uint32_t*)p;
+    sv->in_use = sv->fixed;
+    *out = sv;
+    return TFHE_OK;
+}
+
+extern "C" void sql_server_destroy(sql_server* sv) {
+    if (!sv) return;
+    hipDeviceSynchronize();
+    for (auto* q : sv->active) { if (q->tmp) hipFree(q->tmp); delete q; }
+    for (auto* q : sv->queue) delete q;
+    if (sv->stage) hipFree(sv->stage);
+    if (sv->hsegs) hipHostFree(sv->hsegs);
+    if (sv->hstart) hipHostFree(sv->hstart);
+    delete sv;
+}
+
+extern "C" size_t sql_server_bytes_in_use(const sql_server* sv) { return sv ? sv->in_use : 0; }
+
+extern "C" int sql_server_submit(sql_server* sv, const sql_sum_query* q, uint64_t* id) {
+    if (!sv || !q || !id) return TFHE_EINVAL;
+    tfhe_ctx* c = sv->c;
+    int rc = check_scan(c, q->d_col, q->w, q->op, q->d_lit_a, q->d_lit_b, q->d_sum);
+    if (rc) return rc;
+    if (!q->d_sum_col || !q->rows || q->w > 32) return ctx_fail(c, TFHE_EINVAL, "bad SUM query");
+    auto* sq = new ServerQuery();
+    Builder b(c);
+    const size_t lw = b.lw;
+    Ref col = dev(q->d_col, (size_t)q->w * lw), la = dev(q->d_lit_a, 0), lb = dev(q->d_lit_b, 0);
+    Ref mask = b.tmp(q->rows);
+    const size_t lev = b.predicate(0, q->rows, q->w, q->op, col, la, q->d_lit_b ? &lb : nullptr, mask);
+    b.masked_sum(lev, q->rows, q->w, mask, dev(q->d_sum_col, (size_t)q->w * lw), (uint64_t)(uintptr_t)q->d_sum,
+                 (uint64_t)(uintptr_t)c->d_false);
+    sq->net = std::move(b.net);
+    sq->tmp_bytes = al256(sq->net.tmp_words * b.wb);
+    if (sv->fixed + sq->tmp_bytes > sv->budget) {
+        delete sq;
+        return ctx_fail(c, TFHE_ENOMEM, "query working set exceeds the HBM budget");
+    }
+    sq->id = sv->next_id++;
+    sv->known.insert(sq->id);
+    sv->queue.push_back(sq);
+    *id = sq->id;
+    return TFHE_OK;
+}
+
+static int server_admit(sql_server* sv) {
+    while (!sv->queue.empty() && sv->active.size() < kMaxActive) {
+        ServerQuery* q = sv->queue.front();
+        if (sv->in_use + q->tmp_bytes > sv->budget) break;  // wait for memory to free
+        int rc = hip_check(sv->c, hipMalloc(&q->tmp, q->tmp_bytes ? q->tmp_bytes : 256), "query temporaries");
+        if (rc) return rc;
+        const uint64_t base = (uint64_t)(uintptr_t)q->tmp;
+        auto res = [&](uint64_t a) { return (a & REL) ? base + (a & ~REL) : a; };
+        for (auto& L : q->net.levels) {
+            for (auto& sg : L.segs) {
+                for (int j = 0; j < sg.nin; j++) sg.in[j] = res(sg.in[j]);
+                sg.out = res(sg.out);
+            }
+            for (auto& cp : L.copies) { cp.src = res(cp.src); cp.dst = res(cp.dst); }
+        }
+        sv->in_use += q->tmp_bytes;
+        sv->active.push_back(q);
+        sv->queue.pop_front();
+    }
+    return TFHE_OK;
+}
+
+extern "C" int sql_server_step(sql_server* sv, void* stream, uint32_t* gates, uint32_t* active, uint32_t* queued) {
+    if (!sv) return TFHE_EINVAL;
+    tfhe_ctx* c = sv->c;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = server_admit(sv);
+    if (rc) return rc;
+    const size_t wb = word_bytes(c);
+    size_t nseg = 0;
+    uint32_t total = 0;
+    std::vector<Copy> copies;
+    for (auto* q : sv->active) {
+        if (total >= sv->max_batch || nseg >= kSegCap) break;
+        if (q->level >= q->net.levels.size()) continue;
+        Level& L = q->net.levels[q->level];
+        if (!q->copies_done) {
+            copies.insert(copies.end(), L.copies.begin(), L.copies.end());
+            q->copies_done = true;
+        }
+        while (q->seg < L.segs.size() && total < sv->max_batch && nseg < kSegCap) {
+            Segment sg = L.segs[q->seg];
+            const uint32_t take = std::min<uint32_t>(sg.rows - q->row, sv->max_batch - total);
+            for (int j = 0; j < sg.nin; j++) sg.in[j] += (uint64_t)(q->row * sg.in_stride[j]) * wb;
+            sg.out += (uint64_t)(q->row * sg.out_stride) * wb;
+            sg.rows = take;
+            sv->hsegs[nseg] = sg;
+            sv->hstart[nseg] = total;
+            nseg++;
+            total += take;
+            q->row += take;
+            if (q->row == L.segs[q->seg].rows) { q->seg++; q->row = 0; }
+        }
+        if (q->seg == L.segs.size()) {  // level fully issued; the next tick runs the next one
+            q->level++;
+            q->seg = 0;
+            q->copies_done = false;
+        }
+    }
+    for (auto& cp : copies) {
+        rc = hip_check(c, hipMemcpyAsync((void*)(uintptr_t)cp.dst, (const void*)(uintptr_t)cp.src, cp.bytes,
+                                         hipMemcpyDeviceToDevice, s), "server copy");
+        if (rc) return rc;
+    }
+    if (total) {
+        if ((rc = hip_check(c, hipMemcpyAsync(sv->dsegs, sv->hsegs, nseg * sizeof(Segment), hipMemcpyHostToDevice, s),
+                            "server segments")) ||
+            (rc = hip_check(c, hipMemcpyAsync(sv->dstart, sv->hstart, nseg * 4, hipMemcpyHostToDevice, s),
+                            "server starts")) ||
+            (rc = launch_combine(c, sv->dsegs, sv->dstart, (int)nseg, total, sv->lwe, sv->ptrs, sv->tvi, s)) ||
+            (rc = launch_blind_rotate(c, sv->lwe, nullptr, nullptr, sv->big, total, sv->brws, s)) ||
+            (rc = launch_keyswitch(c, sv->big, nullptr, sv->ptrs, total, s)))
+            return rc;
+    }
+    if ((rc = hip_check(c, hipStreamSynchronize(s), "server tick"))) return rc;
+    // retire finished queries
+    std::vector<ServerQuery*> keep;
+    for (auto* q : sv->active) {
+        if (q->level >= q->net.levels.size()) {
+            sv->done.insert(q->id);
+            hipFree(q->tmp);
+            sv->in_use -= q->tmp_bytes;
+            delete q;
+        } else {
+            keep.push_back(q);
+        }
+    }
+    sv->active.swap(keep);
+    if (gates) *gates = total;
+    if (active) *active = (uint32_t)sv->active.size();
+    if (queued) *queued = (uint32_t)sv->queue.size();
+    return TFHE_OK;
+}
+
+extern "C" int sql_server_done(sql_server* sv, uint64_t id) {
+    if (!sv) return TFHE_EINVAL;
+    if (!sv->known.count(id)) return TFHE_EINVAL;
+    return sv->done.count(id) ? 1 : 0;
 }

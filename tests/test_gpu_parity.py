@@ -274,3 +274,101 @@ def test_errors_are_reported():
         fs.Context(bad, np.zeros(10, dtype=np.uint64), np.zeros(10, dtype=np.uint64))
     # B = 0 is a no-op
     ctx.tfhe_bootstrap_batch(x, x, B=0)
+
+
+def test_tuning_knobs_do_not_change_bits():
+    """Splitting levels into small launches and the alternative MFMA row-pass
+    variant give the same bits as the defaults."""
+    p = si.TOY
+    K = keys_for("toy")
+    ctx = ctx_for("toy")
+    rows, w = 21, 4
+    col1, col2, c1, c2 = _table(p, K, rows, w, 20)
+    lit = _lit(p, K, int(col1[2]), w, 120)
+    outs = []
+    for mb, rp in ((65536, 0), (16, 0), (48, 2), (65536, 4)):
+        ctx.set_tuning(max_batch=mb, row_pass=rp)
+        m, sel = empty(p, rows, p.n + 1), empty(p, rows, w, p.n + 1)
+        ctx.sql_mask_scan(to_dev(p, c1), rows, w, "eq", to_dev(p, lit), m)
+        ctx.sql_masked_select(m, to_dev(p, c2), rows, w, sel)
+        torch.cuda.synchronize()
+        outs.append((from_dev(p, m), from_dev(p, sel)))
+    ctx.set_tuning(max_batch=65536, row_pass=0)
+    for m, sel in outs[1:]:
+        assert np.array_equal(m, outs[0][0]) and np.array_equal(sel, outs[0][1])
+    om = C.mask_rows(p, K, "eq", c1[:3], lit)
+    assert np.array_equal(outs[0][0][:3], om)
+    with pytest.raises(fs.FheError):
+        ctx.set_tuning(row_pass=3)
+
+
+def test_server_isolation_parity_and_admission():
+    """A query's encrypted SUM is the same bits alone, mixed with other queries
+    in the continuous-batching server, and through the direct calls; it
+    matches the oracle; a tiny budget queues queries instead of failing."""
+    p = si.TINY
+    K = keys_for("tiny")
+    ctx = ctx_for("tiny")
+    w = 4
+    specs = [(7, "eq"), (12, "lt"), (5, "gt"), (1, "lt")]
+    qs = []
+    for t, (rows, op) in enumerate(specs):
+        col1, col2, c1, c2 = _table(p, K, rows, w, 40 + t, table_id=t)
+        lit = _lit(p, K, int(col1[0]) if op == "eq" else 9, w, 140 + t)
+        width = fs.sum_width(w, rows)
+        qs.append(dict(col=to_dev(p, c1), sum_col=to_dev(p, c2), rows=rows, w=w, op=op, lit_a=to_dev(p, lit),
+                       width=width, host=(col1, col2, c1, c2, lit)))
+
+    def run_server(indices, budget, stagger):
+        srv = fs.Server(ctx, budget, max_batch=64)
+        outs, ids = {}, {}
+        pending = list(indices)
+        ticks = 0
+        while pending or any(not srv.done(ids[i]) for i in ids):
+            if pending and (ticks % stagger == 0):
+                i = pending.pop(0)
+                outs[i] = empty(p, qs[i]["width"], p.n + 1)
+                q = qs[i]
+                ids[i] = srv.submit(q["col"], q["sum_col"], q["rows"], q["w"], q["op"], q["lit_a"], outs[i])
+            srv.step()
+            ticks += 1
+            assert ticks < 5000
+        srv.close()
+        return {i: from_dev(p, outs[i]) for i in outs}
+
+    alone = {}
+    for i in range(len(qs)):
+        alone.update(run_server([i], 1 << 34, 1))
+    mixed = run_server(list(range(len(qs))), 1 << 34, 3)
+    for i in range(len(qs)):
+        assert np.array_equal(alone[i], mixed[i]), i
+    # direct calls give the same bits
+    q = qs[1]
+    m = empty(p, q["rows"], p.n + 1)
+    ctx.sql_mask_scan(q["col"], q["rows"], w, q["op"], q["lit_a"], m)
+    s_dir = empty(p, q["width"], p.n + 1)
+    ctx.sql_masked_sum(m, q["sum_col"], q["rows"], w, s_dir)
+    torch.cuda.synchronize()
+    assert np.array_equal(from_dev(p, s_dir), alone[1])
+    # oracle end to end for queries 0 and 3, decrypted truth for all
+    for i in (0, 3):
+        col1, col2, c1, c2, lit = qs[i]["host"]
+        be = C.CipherBackend(p, K)
+        masks = [C.predicate(be, qs[i]["op"], list(c1[r]), list(lit)) for r in range(qs[i]["rows"])]
+        sel = [C.select(be, masks[r], list(c2[r])) for r in range(qs[i]["rows"])]
+        want = np.stack(C.sum_tree(be, sel)) if qs[i]["rows"] > 1 else np.stack(sel[0])
+        assert np.array_equal(alone[i], want), i
+    for i, q in enumerate(qs):
+        col1, col2, c1, c2, lit = q["host"]
+        c = int(col1[0]) if q["op"] == "eq" else 9
+        pred = {"eq": col1 == c, "lt": col1 < c, "gt": col1 > c}[q["op"]]
+        assert bits_to_int(dec_bits(p, K, alone[i])) == int((col2 * pred).sum()), i
+    # admission: a budget just above one query's needs still completes all of them
+    srv = fs.Server(ctx, 1 << 34, max_batch=64)
+    base = srv.bytes_in_use()
+    srv.close()
+    tight = run_server(list(range(len(qs))), base + (24 << 10), 1)
+    for i in range(len(qs)):
+        assert np.array_equal(tight[i], alone[i]), i
+    with pytest.raises(fs.FheError):
+        fs.Server(ctx, 1024, max_batch=64)
