@@ -103,6 +103,9 @@ int tfhe_set_kernel(tfhe_ctx* ctx, int kind);
  * Returns TFHE_EINVAL for an unknown key or unsupported value. */
 #define TFHE_TUNE_MAX_BATCH 1
 #define TFHE_TUNE_ROW_PASS 2
+/*   TFHE_TUNE_DIGIT_BLOCKS 0 = form all digit blocks of a CMux step at once when
+ *                        they fit in LDS (default), 1 = one (u,p) block at a time. */
+#define TFHE_TUNE_DIGIT_BLOCKS 3
 int tfhe_set_tuning(tfhe_ctx* ctx, int key, int64_t value);
 
 /* Waits for the stream and reports any asynchronous fault. */
@@ -173,6 +176,26 @@ int sql_scan_batch(tfhe_ctx* ctx, const sql_table_query* q, uint32_t count, int 
 int tfhe_timing_enable(tfhe_ctx* ctx, int on);
 int tfhe_timing_read(tfhe_ctx* ctx, int kind, uint64_t* launches, double* total_ms,
                      uint64_t* cts);
+
+/* ---- radix integers (programmable bootstrapping with look-up tables) ----
+ * An integer is nb blocks of 4-bit messages, least significant block first; a
+ * block value x in [0, 32) (4 message bits + 1 carry bit) is the LWE
+ * encryption of x * 2^q / 64 (the top torus bit is padding).  Each gate is a
+ * linear combination followed by a programmable bootstrap whose test
+ * polynomial encodes a table over Z_32.  Columns are [rows][nb][n+1] words. */
+
+/* d_mask[r] = 16 * [col[r] op lit] as one block (op: SQL_OP_EQ/LT/GT):
+ * block-wise x_i = a_i - c_i + 16 -> {lt, eq, gt}, tree-combined 2*hi + lo.
+ * nb >= 2.  d_lit [nb][n+1]. */
+int sql_radix_mask_scan(tfhe_ctx* ctx, const void* d_col, uint32_t rows, uint32_t nb, int op,
+                        const void* d_lit, void* d_mask, void* hip_stream);
+/* d_out[r][i] = col[r][i] if mask[r] encrypts 16, else 0 (If-Then-Else). */
+int sql_radix_masked_select(tfhe_ctx* ctx, const void* d_mask, const void* d_col, uint32_t rows,
+                            uint32_t nb, void* d_out, void* hip_stream);
+/* d_sum [nb][n+1] = sum of the rows of d_vals [rows][nb][n+1] mod 2^(4 nb):
+ * pairwise row tree of ripple-carry radix additions. */
+int sql_radix_sum(tfhe_ctx* ctx, const void* d_vals, uint32_t rows, uint32_t nb, void* d_sum,
+                  void* hip_stream);
 
 /* ---- continuous-batching query server ----
  * Serves SELECT SUM(col2) WHERE col1 op literal queries (Algorithm 2's mask,

@@ -247,3 +247,116 @@ def resolve(p, x):
     if isinstance(x, list):
         return np.stack([resolve(p, v) for v in x])
     return _value(p, x)
+
+
+# ------------------------------------------------------------ radix circuits
+#
+# Programmable bootstrapping over radix integers (the reading used for the
+# 64-bit workload): an integer is nb blocks of 4-bit messages, least
+# significant block first; a block value x in [0, 32) (4 message bits plus
+# one carry bit) is encrypted as x * delta with delta = 2^q / 64, the top bit
+# of the torus left as padding.  A bootstrap with a table f over Z_32 maps an
+# encryption of x to an encryption of f(x) * delta.
+#   compare a vs c : x_i = a_i - c_i + 16 in [1, 31], r_i = CMP(x_i) with
+#                    CMP = {<16: 0 (lt), 16: 1 (eq), >16: 2 (gt)};
+#                    tree over blocks pairing (0,1),(2,3),...: 2*hi + lo -> COMB
+#                    {0,1,2: 0; 3: 1; 4,5,6: 2}; the root uses ROOT_op, which
+#                    outputs 16 when the relation holds and 0 otherwise.
+#   select         : s_i = SEL(v_i + root), SEL(x) = x - 16 if x >= 16 else 0.
+#   add            : z_i = x_i + y_i + carry_{i-1}; block MSG(z) = z mod 16 and,
+#                    below the top block, carry CARRY(z) = z div 16 (wraps mod 2^(4 nb)).
+#   SUM            : pairwise tree over rows, an odd operand passes up unchanged.
+
+RADIX_P = 32       # plaintext modulus of a block (4 message bits + 1 carry bit)
+RADIX_MSG = 16
+
+
+def radix_tables():
+    """Tables over Z_32 of the radix circuits."""
+    P = RADIX_P
+    cmp_ = [0 if x < 16 else (1 if x == 16 else 2) for x in range(P)]
+    comb = [0 if x <= 2 else (1 if x == 3 else 2) if x <= 6 else 0 for x in range(P)]
+    root = {
+        "lt": [16 if x <= 2 else 0 for x in range(P)],
+        "eq": [16 if x == 3 else 0 for x in range(P)],
+        "gt": [16 if 4 <= x <= 6 else 0 for x in range(P)],
+    }
+    sel = [x - 16 if x >= 16 else 0 for x in range(P)]
+    msg = [x % 16 for x in range(P)]
+    carry = [x // 16 for x in range(P)]
+    return {"cmp": cmp_, "comb": comb, "root_lt": root["lt"], "root_eq": root["eq"], "root_gt": root["gt"],
+            "sel": sel, "msg": msg, "carry": carry}
+
+
+class RadixPlainBackend:
+    """Plaintext semantics: blocks are ints, lin() is the integer combination."""
+
+    def __init__(self):
+        self.t = radix_tables()
+
+    def lin(self, ins, weights, const):
+        return sum(w * x for w, x in zip(weights, ins)) + const
+
+    def pbs(self, x, table):
+        assert 0 <= x < RADIX_P, x
+        return self.t[table][x]
+
+
+class RadixCipherBackend:
+    """Encrypted blocks: lin() is the LWE linear combination, pbs() the
+    programmable bootstrap (blind rotation, extraction, key switch)."""
+
+    def __init__(self, p, keys):
+        from . import lut_testv
+        self.p, self.keys = p, keys
+        self.delta = 1 << (p.q - 6)
+        self.tv = {name: lut_testv(p, RADIX_P, np.array(tab, dtype=np.uint64), self.delta)
+                   for name, tab in radix_tables().items()}
+        self.count = 0
+
+    def lin(self, ins, weights, const):
+        return lincomb(self.p, np.stack(ins), list(weights), (const * self.delta) & qmask(self.p.q))
+
+    def pbs(self, x, table):
+        from . import pbs
+        self.count += 1
+        return pbs(self.p, self.keys.bsk, self.keys.ksk, x, self.tv[table])
+
+
+def radix_compare(be, op, a, c):
+    """Encrypted 16 * [a op c] (op in lt, eq, gt) from block lists a, c."""
+    r = [be.pbs(be.lin([a[i], c[i]], [1, -1], 16), "cmp") for i in range(len(a))]
+    assert len(r) >= 2
+    while len(r) > 1:
+        root = len(r) == 2
+        nxt = [be.pbs(be.lin([r[2 * i + 1], r[2 * i]], [2, 1], 0), f"root_{op}" if root else "comb")
+               for i in range(len(r) // 2)]
+        if len(r) % 2:
+            nxt.append(r[-1])
+        r = nxt
+    return r[0]
+
+
+def radix_select(be, m, v):
+    return [be.pbs(be.lin([v[i], m], [1, 1], 0), "sel") for i in range(len(v))]
+
+
+def radix_add(be, x, y):
+    out, carry = [], None
+    for i in range(len(x)):
+        ins, ws = ([x[i], y[i]], [1, 1]) if carry is None else ([x[i], y[i], carry], [1, 1, 1])
+        z = be.lin(ins, ws, 0)
+        out.append(be.pbs(z, "msg"))
+        if i + 1 < len(x):
+            carry = be.pbs(z, "carry")
+    return out
+
+
+def radix_sum(be, operands):
+    level = [list(o) for o in operands]
+    while len(level) > 1:
+        nxt = [radix_add(be, level[2 * i], level[2 * i + 1]) for i in range(len(level) // 2)]
+        if len(level) % 2:
+            nxt.append(level[-1])
+        level = nxt
+    return level[0]

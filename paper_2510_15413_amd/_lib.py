@@ -34,9 +34,11 @@ EXPORTS = [
     "tfhe_lwe_encrypt", "tfhe_lwe_phase", "tfhe_timing_enable", "tfhe_timing_read",
     "tfhe_set_tuning", "sql_server_create", "sql_server_destroy", "sql_server_submit",
     "sql_server_step", "sql_server_done", "sql_server_bytes_in_use",
+    "sql_radix_mask_scan", "sql_radix_masked_select", "sql_radix_sum",
 ]
 TFHE_TUNE_MAX_BATCH = 1
 TFHE_TUNE_ROW_PASS = 2
+TFHE_TUNE_DIGIT_BLOCKS = 3
 
 
 class FheError(RuntimeError):
@@ -101,6 +103,9 @@ def load():
         "sql_server_step": (i32, [vp, vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]),
         "sql_server_done": (i32, [vp, u64]),
         "sql_server_bytes_in_use": (sz, [vp]),
+        "sql_radix_mask_scan": (i32, [vp, vp, u32, u32, i32, vp, vp, vp]),
+        "sql_radix_masked_select": (i32, [vp, vp, vp, u32, u32, vp, vp]),
+        "sql_radix_sum": (i32, [vp, vp, u32, u32, vp, vp]),
         "tfhe_timing_read": (i32, [vp, i32, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(u64)]),
     }
@@ -197,8 +202,10 @@ class Context:
                                          ctypes.byref(cts)), "tfhe_timing_read")
         return n.value, ms.value, cts.value
 
-    def set_tuning(self, max_batch=None, row_pass=None):
+    def set_tuning(self, max_batch=None, row_pass=None, digit_blocks=None):
         L = load()
+        if digit_blocks is not None:
+            self._rc(L.tfhe_set_tuning(self._h, TFHE_TUNE_DIGIT_BLOCKS, int(digit_blocks)), "tfhe_set_tuning")
         if max_batch is not None:
             self._rc(L.tfhe_set_tuning(self._h, TFHE_TUNE_MAX_BATCH, int(max_batch)), "tfhe_set_tuning")
         if row_pass is not None:
@@ -249,6 +256,23 @@ class Context:
         self._rc(load().sql_masked_sum(self._h, _ptr(mask), _ptr(col), rows, w, _ptr(out), ctypes.byref(width),
                                        _stream(stream)), "sql_masked_sum")
         return width.value
+
+    def sql_radix_mask_scan(self, col, rows, nb, op, lit, mask, stream=None):
+        for t, nm in ((col, "col"), (lit, "lit"), (mask, "mask")):
+            _check_dev(t, nm)
+        self._rc(load().sql_radix_mask_scan(self._h, _ptr(col), rows, nb, SQL_OPS.get(op, op), _ptr(lit), _ptr(mask),
+                                            _stream(stream)), "sql_radix_mask_scan")
+
+    def sql_radix_masked_select(self, mask, col, rows, nb, out, stream=None):
+        for t, nm in ((mask, "mask"), (col, "col"), (out, "out")):
+            _check_dev(t, nm)
+        self._rc(load().sql_radix_masked_select(self._h, _ptr(mask), _ptr(col), rows, nb, _ptr(out), _stream(stream)),
+                 "sql_radix_masked_select")
+
+    def sql_radix_sum(self, vals, rows, nb, out, stream=None):
+        for t, nm in ((vals, "vals"), (out, "out")):
+            _check_dev(t, nm)
+        self._rc(load().sql_radix_sum(self._h, _ptr(vals), rows, nb, _ptr(out), _stream(stream)), "sql_radix_sum")
 
     def sql_scan_batch(self, queries, use_graph=False, stream=None):
         """queries: list of dicts with col, rows, w, op, lit_a, lit_b, mask, sel_col, sel_out."""

@@ -361,7 +361,7 @@ int dispatch_dall(tfhe_ctx* c, const BrArgs& a, hipStream_t s) {
                                ? (size_t)c->prop.maxSharedMemoryPerMultiProcessor
                                : (size_t)160 * 1024;
     size_t need = lds_need(c, true);
-    if (need <= max_lds) return launch_t<T, R, RP, true>(c, a, need, s);
+    if (need <= max_lds && c->digit_blocks == 0) return launch_t<T, R, RP, true>(c, a, need, s);
     need = lds_need(c, false);
     if (need > max_lds) return ctx_fail(c, TFHE_EINVAL, "parameters exceed LDS capacity of the MFMA kernel");
     return launch_t<T, R, RP, false>(c, a, need, s);

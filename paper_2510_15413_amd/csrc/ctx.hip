@@ -175,6 +175,7 @@ extern "C" void tfhe_ctx_destroy(tfhe_ctx* c) {
     if (c->d_ksk) hipFree(c->d_ksk);
     if (c->d_gate_tv) hipFree(c->d_gate_tv);
     if (c->d_false) hipFree(c->d_false);
+    if (c->d_radix_tv) hipFree(c->d_radix_tv);
     if (c->ws) hipFree(c->ws);
     delete c;
 }
@@ -195,6 +196,11 @@ extern "C" int tfhe_set_tuning(tfhe_ctx* c, int key, int64_t value) {
     if (key == TFHE_TUNE_MAX_BATCH) {
         if (value < 16 || value > (1 << 22)) return ctx_fail(c, TFHE_EINVAL, "max batch must be in [16, 2^22]");
         c->max_batch = (uint32_t)value;
+        return TFHE_OK;
+    }
+    if (key == TFHE_TUNE_DIGIT_BLOCKS) {
+        if (value != 0 && value != 1) return ctx_fail(c, TFHE_EINVAL, "digit blocks must be 0 or 1");
+        c->digit_blocks = (int)value;
         return TFHE_OK;
     }
     if (key == TFHE_TUNE_ROW_PASS) {

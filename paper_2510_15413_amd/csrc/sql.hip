@@ -93,6 +93,7 @@ struct Level {
 struct Netlist {
     std::vector<Level> levels;
     size_t tmp_words = 0;  // words of temporaries used (relative addresses)
+    const void* lut_table = nullptr;  // test polynomials indexed by Segment::lut
 };
 
 // Temporaries are addressed relative to a base chosen at execution time:
@@ -168,6 +169,100 @@ struct Builder {
         s.rows = rows;
         s.lut = -1;
         level_push(lev, s);
+    }
+
+    // Linear combination (constant in torus words) followed by a bootstrap
+    // with test polynomial `lut` of the netlist's table.
+    void lin(size_t lev, uint32_t rows, std::vector<std::pair<const Ref*, int>> ins, uint64_t cst, Ref out, int lut) {
+        Segment s{};
+        int k = 0;
+        for (auto& pr : ins) {
+            s.in[k] = pr.first->addr;
+            s.in_stride[k] = pr.first->stride;
+            s.w[k] = pr.second;
+            k++;
+        }
+        s.nin = k;
+        s.cst = wrap((int64_t)cst);
+        s.out = out.addr;
+        s.out_stride = out.stride;
+        s.rows = rows;
+        s.lut = lut;
+        level_push(lev, s);
+    }
+
+    // ---- radix circuits (blocks of 4-bit messages + 1 carry bit, delta = 2^q/64)
+    enum { L_CMP = 0, L_COMB, L_ROOT_LT, L_ROOT_EQ, L_ROOT_GT, L_SEL, L_MSG, L_CARRY, L_COUNT };
+    uint64_t delta() const { return 1ull << ((c->q == 32 ? 32 : 64) - 6); }
+
+    size_t radix_compare(size_t lev, uint32_t rows, uint32_t nb, int op, const Ref& col, const Ref& lit, Ref out) {
+        std::vector<Ref> r;
+        for (uint32_t i = 0; i < nb; i++) {
+            Ref a = bit(col, i, lw, wb), ci = bit(lit, i, lw, wb);
+            Ref o = tmp(rows);
+            lin(lev, rows, {{&a, 1}, {&ci, -1}}, 16 * delta(), o, L_CMP);
+            r.push_back(o);
+        }
+        lev++;
+        const int root = op == SQL_OP_LT ? L_ROOT_LT : op == SQL_OP_EQ ? L_ROOT_EQ : L_ROOT_GT;
+        while (r.size() > 1) {
+            std::vector<Ref> nxt;
+            const bool last = r.size() == 2;
+            for (size_t i = 0; i < r.size() / 2; i++) {
+                Ref o = last ? out : tmp(rows);
+                lin(lev, rows, {{&r[2 * i + 1], 2}, {&r[2 * i], 1}}, 0, o, last ? root : L_COMB);
+                nxt.push_back(o);
+            }
+            if (r.size() % 2) nxt.push_back(r.back());
+            r.swap(nxt);
+            lev++;
+        }
+        return lev;
+    }
+    size_t radix_select(size_t lev, uint32_t rows, uint32_t nb, const Ref& mask, const Ref& col, Ref out) {
+        for (uint32_t i = 0; i < nb; i++) {
+            Ref v = bit(col, i, lw, wb), o = bit(out, i, lw, wb);
+            lin(lev, rows, {{&v, 1}, {&mask, 1}}, 0, o, L_SEL);
+        }
+        return lev + 1;
+    }
+    // Pairwise row tree of ripple-carry additions; operands [rows][nb] at `vals`.
+    size_t radix_sum(size_t lev, uint32_t rows, uint32_t nb, Ref vals, uint64_t sum) {
+        Ref cur = vals;
+        uint32_t cnt = rows;
+        auto at = [&](const Ref& base, uint32_t opd, uint32_t i, int64_t stride) -> Ref {
+            return Ref{base.addr + ((uint64_t)opd * base.stride + (uint64_t)i * lw) * wb, stride};
+        };
+        if (rows == 1) {
+            copy_push(lev, cur.addr, sum, (uint64_t)nb * lw * wb);
+            return lev + 1;
+        }
+        while (cnt > 1) {
+            const uint32_t pairs = cnt / 2;
+            const bool odd = cnt & 1;
+            const bool last = pairs + (odd ? 1 : 0) == 1;
+            Ref res;
+            if (last) res = Ref{sum, (int64_t)(nb * lw)};
+            else { res = tmp((pairs + (odd ? 1 : 0)) * nb); res.stride = (int64_t)(nb * lw); }
+            const int64_t xs = 2 * cur.stride;
+            Ref carry{};
+            for (uint32_t i = 0; i < nb; i++) {
+                Ref x = at(cur, 0, i, xs), y = at(cur, 1, i, xs);
+                std::vector<std::pair<const Ref*, int>> ins = {{&x, 1}, {&y, 1}};
+                if (i) ins.push_back({&carry, 1});
+                lin(lev + i, pairs, ins, 0, at(res, 0, i, res.stride), L_MSG);
+                if (i + 1 < nb) {
+                    Ref nc = tmp(pairs);
+                    lin(lev + i, pairs, ins, 0, nc, L_CARRY);
+                    carry = nc;
+                }
+            }
+            if (odd) copy_push(lev, at(cur, cnt - 1, 0, 0).addr, at(res, pairs, 0, 0).addr, (uint64_t)nb * lw * wb);
+            lev += nb;
+            cnt = pairs + (odd ? 1 : 0);
+            cur = res;
+        }
+        return lev;
     }
 
     static Ref bit(const Ref& base, uint32_t j, size_t lw_, size_t wb_) {
@@ -310,8 +405,10 @@ struct Exec {
             max_gates = std::max(max_gates, g);
             nseg_total += lv.segs.size();
         }
-        if (!max_gates) return TFHE_OK;
-        const uint32_t chunk = (uint32_t)std::min<size_t>(max_gates, max_batch);
+        size_t ncopies = 0;
+        for (auto& lv : net.levels) ncopies += lv.copies.size();
+        if (!max_gates && !ncopies) return TFHE_OK;
+        const uint32_t chunk = (uint32_t)std::max<size_t>(1, std::min<size_t>(max_gates, max_batch));
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
         const size_t tmp_b = al(net.tmp_words * wb);
         const size_t lwe_b = al((size_t)chunk * lw * wb);
@@ -402,7 +499,9 @@ struct Exec {
             if (rc) break;
             if (!pc.total) continue;
             if ((rc = launch_combine(c, dsegs + pc.seg_off, dstart + pc.seg_off, pc.nseg, pc.total, lwe, ptrs, tvi, rs))) break;
-            if ((rc = launch_blind_rotate(c, lwe, nullptr, nullptr, big, pc.total, brws, rs))) break;
+            if ((rc = launch_blind_rotate(c, lwe, net.lut_table, net.lut_table ? tvi : nullptr, big, pc.total,
+                                          brws, rs)))
+                break;
             if ((rc = launch_keyswitch(c, big, nullptr, ptrs, pc.total, rs))) break;
         }
         if (use_graph) {
@@ -735,4 +834,90 @@ extern "C" int sql_server_done(sql_server* sv, uint64_t id) {
     if (!sv) return TFHE_EINVAL;
     if (!sv->known.count(id)) return TFHE_EINVAL;
     return sv->done.count(id) ? 1 : 0;
+}
+
+// ------------------------------------------------------------ radix C ABI
+
+// Test polynomial of a table f over Z_p (p = 32 boxes on the half torus):
+// coefficient j encodes f(m(j)), m(j) = floor((j p + N/2) / N); the last
+// half-box (m(j) = p) holds -f(0) so phases just below 0 return f(0).
+template <typename T>
+static void lut_poly(int N, const int* f, int p, T delta, T* out) {
+    for (int j = 0; j < N; j++) {
+        const int64_t m = ((int64_t)j * p + N / 2) / N;
+        out[j] = m >= p ? (T)(0 - delta * (T)f[0]) : (T)(delta * (T)f[m]);
+    }
+}
+
+static int radix_tables_ready(tfhe_ctx* c) {
+    if (c->d_radix_tv) return TFHE_OK;
+    const int P = 32, N = (int)c->p.N;
+    int tab[8][32];
+    for (int x = 0; x < P; x++) {
+        tab[0][x] = x < 16 ? 0 : (x == 16 ? 1 : 2);            // cmp
+        tab[1][x] = x <= 2 ? 0 : (x == 3 ? 1 : (x <= 6 ? 2 : 0));  // comb
+        tab[2][x] = x <= 2 ? 16 : 0;                           // root lt
+        tab[3][x] = x == 3 ? 16 : 0;                           // root eq
+        tab[4][x] = (x >= 4 && x <= 6) ? 16 : 0;               // root gt
+        tab[5][x] = x >= 16 ? x - 16 : 0;                      // select
+        tab[6][x] = x % 16;                                    // message
+        tab[7][x] = x / 16;                                    // carry
+    }
+    const size_t wb = word_bytes(c);
+    std::vector<uint8_t> host(8 * (size_t)N * wb);
+    for (int t = 0; t < 8; t++) {
+        if (c->q == 32) lut_poly<uint32_t>(N, tab[t], P, (uint32_t)1u << 26, (uint32_t*)host.data() + (size_t)t * N);
+        else lut_poly<uint64_t>(N, tab[t], P, (uint64_t)1ull << 58, (uint64_t*)host.data() + (size_t)t * N);
+    }
+    int rc = hip_check(c, hipMalloc(&c->d_radix_tv, host.size()), "radix tables");
+    if (rc) return rc;
+    return hip_check(c, hipMemcpy(c->d_radix_tv, host.data(), host.size(), hipMemcpyHostToDevice), "radix tables");
+}
+
+extern "C" int sql_radix_mask_scan(tfhe_ctx* c, const void* d_col, uint32_t rows, uint32_t nb, int op,
+                                   const void* d_lit, void* d_mask, void* stream) {
+    if (!c) return TFHE_EINVAL;
+    if (!rows) return TFHE_OK;
+    if (!d_col || !d_lit || !d_mask) return ctx_fail(c, TFHE_EINVAL, "null ciphertext pointer");
+    if (nb < 2 || nb > 32) return ctx_fail(c, TFHE_ESHAPE, "radix integers need 2..32 blocks");
+    if (op != SQL_OP_LT && op != SQL_OP_EQ && op != SQL_OP_GT) return ctx_fail(c, TFHE_EINVAL, "radix op must be EQ, LT or GT");
+    int rc = radix_tables_ready(c);
+    if (rc) return rc;
+    Builder b(c);
+    const size_t lw = b.lw;
+    b.net.lut_table = c->d_radix_tv;
+    b.radix_compare(0, rows, nb, op, dev(d_col, (size_t)nb * lw), dev(d_lit, 0), dev(d_mask, lw));
+    Exec ex(c, (hipStream_t)stream);
+    return ex.run(b.net, false);
+}
+
+extern "C" int sql_radix_masked_select(tfhe_ctx* c, const void* d_mask, const void* d_col, uint32_t rows, uint32_t nb,
+                                       void* d_out, void* stream) {
+    if (!c) return TFHE_EINVAL;
+    if (!rows) return TFHE_OK;
+    if (!d_mask || !d_col || !d_out) return ctx_fail(c, TFHE_EINVAL, "null ciphertext pointer");
+    if (nb < 1 || nb > 32) return ctx_fail(c, TFHE_ESHAPE, "radix integers need 1..32 blocks");
+    int rc = radix_tables_ready(c);
+    if (rc) return rc;
+    Builder b(c);
+    const size_t lw = b.lw;
+    b.net.lut_table = c->d_radix_tv;
+    b.radix_select(0, rows, nb, dev(d_mask, lw), dev(d_col, (size_t)nb * lw), dev(d_out, (size_t)nb * lw));
+    Exec ex(c, (hipStream_t)stream);
+    return ex.run(b.net, false);
+}
+
+extern "C" int sql_radix_sum(tfhe_ctx* c, const void* d_vals, uint32_t rows, uint32_t nb, void* d_sum, void* stream) {
+    if (!c) return TFHE_EINVAL;
+    if (!d_vals || !d_sum) return ctx_fail(c, TFHE_EINVAL, "null ciphertext pointer");
+    if (!rows) return ctx_fail(c, TFHE_ESHAPE, "SUM needs at least one row");
+    if (nb < 1 || nb > 32) return ctx_fail(c, TFHE_ESHAPE, "radix integers need 1..32 blocks");
+    int rc = radix_tables_ready(c);
+    if (rc) return rc;
+    Builder b(c);
+    const size_t lw = b.lw;
+    b.net.lut_table = c->d_radix_tv;
+    b.radix_sum(0, rows, nb, dev(d_vals, (size_t)nb * lw), (uint64_t)(uintptr_t)d_sum);
+    Exec ex(c, (hipStream_t)stream);
+    return ex.run(b.net, false);
 }
