@@ -222,6 +222,90 @@ def serve(args):
                       "table_rows": R, "hbm_budget_bytes": budget, "rates": results}), flush=True)
 
 
+def pbs64(args):
+    """64-bit programmable bootstrapping (n=750, N=2048, l=4, Bg=2^6, KS 2^3x6):
+    32-bit columns as 8 radix blocks of 4 bits.  mask(col1 < c) by block-wise
+    LUT comparison (4 levels) and the masked select of col2 (1 level) over a
+    row sample (--rows) of the 65,536-row table measure throughput; the masked
+    SUM mod 2^32 -- a row tree whose every level is 8 sequential block
+    levels -- is timed on the first --sum-rows selected rows."""
+    import numpy as np
+    import torch
+    import seeded_inputs as si
+    import paper_2510_15413_amd as fs
+    p = si.PBS64
+    nb = 8
+    rows = min(args.rows, 65536)
+    srows = min(args.sum_rows, rows)
+    seed = si.DATA_SEED_BASE + 4
+    t_setup = time.perf_counter()
+    s, S, bsk, ksk = fs.tfhe_keygen(p, si.KEY_SEED_BASE + 4)
+    ctx = fs.Context(p, bsk, ksk)
+    del bsk, ksk
+    dev = torch.device("cuda")
+    col1, col2 = si.table(seed, rows, 32)
+    c = int(si.uniform_ints(seed, si.TAG_LITERAL, 1, 32)[0])
+    delta = 1 << 58
+
+    def enc(vals, tag):
+        v = torch.as_tensor(vals.astype("int64"), device=dev)
+        bl = (v[:, None] >> (4 * torch.arange(nb, device=dev))) & 15
+        mu = (bl.reshape(-1) * delta).contiguous()
+        return fs.tfhe_lwe_encrypt(p, seed, s, mu, tag_hi=tag).reshape(len(vals), nb, p.n + 1)
+
+    c1, c2 = enc(col1, 1), enc(col2, 2)
+    lit = enc(np.array([c], dtype=np.uint64), 3)[0]
+    mask = torch.empty((rows, p.n + 1), dtype=torch.int64, device=dev)
+    sel = torch.empty((rows, nb, p.n + 1), dtype=torch.int64, device=dev)
+    tot = torch.empty((nb, p.n + 1), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    log(f"pbs64 setup {time.perf_counter() - t_setup:.1f} s")
+    ctx.timing_enable(True)
+    t0 = time.perf_counter()
+    ctx.sql_radix_mask_scan(c1, rows, nb, "lt", lit, mask)
+    torch.cuda.synchronize()
+    t_mask = time.perf_counter() - t0
+    log(f"pbs64 mask over {rows} rows: {t_mask:.2f} s")
+    t0 = time.perf_counter()
+    ctx.sql_radix_masked_select(mask, c2, rows, nb, sel)
+    torch.cuda.synchronize()
+    t_sel = time.perf_counter() - t0
+    log(f"pbs64 select: {t_sel:.2f} s")
+    br_n, br_ms, br_cts = ctx.timing_read("br")
+    t0 = time.perf_counter()
+    ctx.sql_radix_sum(sel[:srows].contiguous(), srows, nb, tot)
+    torch.cuda.synchronize()
+    t_sum = time.perf_counter() - t0
+    log(f"pbs64 sum of {srows} rows: {t_sum:.2f} s")
+    ctx.timing_enable(False)
+
+    def dec(cts):
+        ph = fs.tfhe_lwe_phase(p, s, cts).cpu().numpy().view(np.uint64)
+        return (((ph + np.uint64(delta // 2)) // np.uint64(delta)) % np.uint64(64)).astype(np.int64)
+    m = dec(mask)
+    tb = dec(tot)
+    got = sum(int(b) << (4 * i) for i, b in enumerate(tb))
+    pred = col1 < c
+    ok_mask = bool((m == np.where(pred, 16, 0)).all())
+    ok_sum = got == int((col2[:srows].astype(object) * pred[:srows]).sum()) % (1 << 32)
+    ops = int8_ops_per_bootstrap(p)
+    ms_pbs = rows * (2 * nb - 1) + rows * nb
+    sum_pbs = (srows - 1) * (2 * nb - 1)
+    sum_levels = nb * max(0, (srows - 1).bit_length())
+    res = {"workload": "pbs64", "params": "q=64 n=750 N=2048 l=4 Bg=2^6 ks 2^3x6, 8 blocks x 4 bits",
+           "rows_sampled": rows, "rows_full": 65536,
+           "mask_select": {"pbs": ms_pbs, "seconds": round(t_mask + t_sel, 3),
+                           "pbs_per_s": round(ms_pbs / (t_mask + t_sel), 1),
+                           "rows_per_s": round(rows / (t_mask + t_sel), 2),
+                           "br_launches": br_n, "br_ms": round(br_ms, 1),
+                           "br_achieved_int8_tops": round(br_cts * ops / (br_ms * 1e-3) / 1e12, 1) if br_ms else 0},
+           "sum": {"rows": srows, "pbs": sum_pbs, "sequential_levels": sum_levels, "seconds": round(t_sum, 2),
+                   "seconds_per_level": round(t_sum / max(1, sum_levels), 3)},
+           "ops_per_pbs": ops, "decrypt_ok": {"mask": ok_mask, "sum": bool(ok_sum)}}
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
 def kernel_only(p):
     import torch
     import seeded_inputs as si
@@ -256,13 +340,14 @@ def main():
     ap.add_argument("--rows", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
-    ap.add_argument("--workload", default="std", choices=["std", "batch16", "serve"],
+    ap.add_argument("--workload", default="std", choices=["std", "batch16", "serve", "pbs64"],
                     help="std: the headline 4096-row scan; batch16: 16 uneven tables at toy "
                          "parameters in one level-batched hipGraph schedule")
     ap.add_argument("--autotune", action="store_true", help="batch16: tune the executor knobs first")
     ap.add_argument("--rates", default="1,2,4,8,16,32,64", help="serve: Poisson rates (queries/s)")
     ap.add_argument("--queries", type=int, default=16, help="serve: queries per rate")
     ap.add_argument("--max-rows", type=int, default=1 << 20, help="serve: largest table prefix")
+    ap.add_argument("--sum-rows", type=int, default=4, help="pbs64: rows in the timed SUM tree")
     ap.add_argument("--kernel-only", action="store_true",
                     help="profiling mode: one 4096-ciphertext MFMA blind rotation, one key switch and a "
                          "256 MiB device copy (the counter calibration), then exit")
@@ -284,6 +369,8 @@ def main():
         return batch16(args)
     if args.workload == "serve":
         return serve(args)
+    if args.workload == "pbs64":
+        return pbs64(args)
     rows, w = args.rows, 8
     kseed, dseed = si.KEY_SEED_BASE + 2, si.DATA_SEED_BASE + 2
     dev = torch.device("cuda")
