@@ -51,12 +51,17 @@ FHE_DEV size_t acc_idx(int N, int v, int j, int c) {
 // in the MFMA B-fragment layout: block (u*l+p, chunk) of 1 KB, lane (g,c) holds
 // the 16 digits of coefficients 64*chunk + 16*g + 0..15 of ciphertext c.
 // U components starting at u_lo; p_only >= 0 keeps only that level (block 0).
-// The accumulator loads of up to 8 work items per thread are issued together.
+// A work item is 4 consecutive coefficients of one ciphertext: its own 4
+// words are one 16-byte group of the accumulator layout and the 4 rotated
+// words straddle at most two such groups, so an item takes three vector
+// loads; the loads of G items are issued together.
 template <typename T, int R, int U>
 FHE_DEV void digits_phase(const T* __restrict__ src, const uint16_t* abar, int n, int i,
                           int8_t* dbuf, int u_lo, int p_only, int l, int bgb) {
+    typedef T vec4 __attribute__((ext_vector_type(4)));
     constexpr int N = R * 64;
-    constexpr int ITEMS = CTS * U * (N / 4);
+    constexpr int NG = N / 4;  // 4-word groups per component
+    constexpr int ITEMS = CTS * U * NG;
     constexpr int IPT = (ITEMS + THREADS - 1) / THREADS;
     constexpr int G = IPT < 4 ? IPT : 4;
     const int lb = l * bgb;
@@ -68,44 +73,61 @@ FHE_DEV void digits_phase(const T* __restrict__ src, const uint16_t* abar, int n
     const int ab = abar[c * n + i];
     const int neg = ab >= N;
     const int es = neg ? ab - N : ab;
+    // coefficient 4kg+e reads rotated index 4kg+e-es: group kg-qs (+1), lane sh
+    const int sh = (4 - (es & 3)) & 3;
+    const int qs = (es + 3) >> 2;  // 4kg - es = 4(kg - qs) + sh
     for (int k0 = 0; k0 < IPT; k0 += G) {
-        T dv[G][4], rv[G][4];
+        vec4 dv[G], r0[G], r1[G];
+        int kq[G];
 #pragma unroll
         for (int k = 0; k < G; k++) {
             const int it = threadIdx.x + (k0 + k) * THREADS;
             if (ITEMS % THREADS != 0 && it >= ITEMS) continue;
             const int rest = it >> 4;
-            const int kg = rest & (N / 4 - 1);
-            const int u = u_lo + rest / (N / 4);
-            const T* P = src + (size_t)u * (N / 4) * CTS * 4;
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                dv[k][e] = P[((size_t)kg * CTS + c) * 4 + e];
-                const int sidx = 4 * kg + e - es;
-                const int x = sidx >= 0 ? sidx : sidx + N;
-                const T v = P[((size_t)(x >> 2) * CTS + c) * 4 + (x & 3)];
-                rv[k][e] = ((sidx < 0) != (neg != 0)) ? (T)(0 - v) : v;
-            }
+            const int kg = rest & (NG - 1);
+            const int u = u_lo + rest / NG;
+            const vec4* P = (const vec4*)(src + (size_t)u * NG * CTS * 4) + c;
+            const int q0 = kg - qs;
+            kq[k] = q0;
+            dv[k] = P[kg * CTS];
+            r0[k] = P[(q0 & (NG - 1)) * CTS];
+            r1[k] = P[((q0 + 1) & (NG - 1)) * CTS];
         }
 #pragma unroll
         for (int k = 0; k < G; k++) {
             const int it = threadIdx.x + (k0 + k) * THREADS;
             if (ITEMS % THREADS != 0 && it >= ITEMS) continue;
             const int rest = it >> 4;
-            const int kg = rest & (N / 4 - 1);
-            const int u = u_lo + rest / (N / 4);
+            const int kg = rest & (NG - 1);
+            const int u = u_lo + rest / NG;
+            // negacyclic sign: a group below zero wraps with a sign flip
+            const bool n0 = (kq[k] < 0) != (neg != 0);
+            const bool n1 = (kq[k] + 1 < 0) != (neg != 0);
             uint32_t y[4];
 #pragma unroll
-            for (int e = 0; e < 4; e++) y[e] = (uint32_t)round_top<T>((T)(rv[k][e] - dv[k][e]), lb) + off;
+            for (int e = 0; e < 4; e++) {
+                const int x = e + sh;  // 0..6
+                T v;
+                bool ng;
+                if (x < 4) {
+                    v = x == 0 ? r0[k][0] : x == 1 ? r0[k][1] : x == 2 ? r0[k][2] : r0[k][3];
+                    ng = n0;
+                } else {
+                    v = x == 4 ? r1[k][0] : x == 5 ? r1[k][1] : r1[k][2];
+                    ng = n1;
+                }
+                const T rv = ng ? (T)(0 - v) : v;
+                y[e] = (uint32_t)round_top<T>((T)(rv - dv[k][e]), lb) + off;
+            }
             const int j0 = 4 * kg;
             const int ch = j0 >> 6, g = (j0 >> 4) & 3, bo = j0 & 15;
             for (int p = 0; p < l; p++) {
                 if (p_only >= 0 && p != p_only) continue;
-                const int sh = (l - 1 - p) * bgb;
+                const int shp = (l - 1 - p) * bgb;
                 uint32_t packed = 0;
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
-                    const int d = (int)((y[e] >> sh) & bgm) - half;
+                    const int d = (int)((y[e] >> shp) & bgm) - half;
                     packed |= ((uint32_t)(d & 0xFF)) << (8 * e);
                 }
                 const int blk = p_only >= 0 ? 0 : (u * l + p);
@@ -159,22 +181,33 @@ FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr,
             v4i acc[RP];
 #pragma unroll
             for (int a = 0; a < RP; a++) acc[a] = v4i{0, 0, 0, 0};
-            // diagonals d = c - a (local); the raw LDS loads of diagonal d+1 are
-            // issued before the MFMAs of diagonal d and combined after them
-            const int dg0 = -(RP - 1) + cg * CP - pass * RP;
-            v4i A = afrag_combine(afrag_raw(S, lanebase + 64 * dg0), sh);
+            // Diagonals d = c - a (local) in wrapped pairs: iteration s takes
+            // d = s for a <= CP-1-s and d = s - CP for the other a, so every
+            // iteration issues RP independent MFMAs (one per accumulator).
+            // The raw LDS loads of iteration s+1 are issued before the MFMAs
+            // of iteration s and combined after them.
+            const int db = lanebase + 64 * (cg * CP - pass * RP);
+            ARaw r0 = afrag_raw(S, db), r1;
+            v4i A0 = afrag_combine(r0, sh), A1 = A0;
 #pragma unroll
-            for (int d = -(RP - 1); d <= CP - 1; d++) {
-                ARaw nxt;
-                if (d < CP - 1) nxt = afrag_raw(S, lanebase + 64 * (d + 1 + cg * CP - pass * RP));
+            for (int s = 0; s < CP; s++) {
+                const bool wrap_next = s + 1 >= CP - RP + 1;
+                if (s + 1 < CP) {
+                    r0 = afrag_raw(S, db + 64 * (s + 1));
+                    if (wrap_next) r1 = afrag_raw(S, db + 64 * (s + 1 - CP));
+                }
 #pragma unroll
                 for (int a = 0; a < RP; a++) {
-                    const int cl = a + d;
-                    if (cl >= 0 && cl < CP)
-                        acc[a] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, bf[cl], acc[a], 0, 0, 0);
+                    if (a + s < CP)
+                        acc[a] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A0, bf[a + s], acc[a], 0, 0, 0);
+                    else
+                        acc[a] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A1, bf[a + s - CP], acc[a], 0, 0, 0);
                 }
                 __builtin_amdgcn_sched_barrier(0);
-                if (d < CP - 1) A = afrag_combine(nxt, sh);
+                if (s + 1 < CP) {
+                    A0 = afrag_combine(r0, sh);
+                    if (wrap_next) A1 = afrag_combine(r1, sh);
+                }
             }
 #pragma unroll
             for (int a = 0; a < RP; a++)
@@ -260,17 +293,36 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     T* src = ws0;
     T* dst = ws1;
     int t = 0;  // linear key-block counter over (i, pass, ub)
+    // With one pass and in-place accumulators each wave keeps its own rows
+    // in registers across steps (the fold accumulates straight into them) and
+    // only stores them for the next step's digit phase.
+    constexpr bool REGACC = DALL && NPASS == 1;
+    typedef T vec4 __attribute__((ext_vector_type(4)));
+    constexpr size_t STEP4 = (size_t)(64 / 4) * CTS * 4;  // 4 row tiles further
+    const size_t rbase = acc_idx<T>(N, v, 16 * jr + 4 * (lane >> 4), lane & 15);
+    T accr[REGACC ? RP : 1][4];
+    if (REGACC) {
+#pragma unroll
+        for (int q = 0; q < (REGACC ? RP : 1); q++) {
+            const vec4 x = *(const vec4*)(ws0 + rbase + q * STEP4);
+#pragma unroll
+            for (int e = 0; e < 4; e++) accr[q][e] = x[e];
+        }
+    }
     for (int i = 0; i < n; i++) {
         if (DALL) {
             digits_phase<T, R, 2>(src, abar, n, i, dbuf, 0, -1, l, a.bg_bits);
             __syncthreads();
         }
         for (int pass = 0; pass < NPASS; pass++) {
-            T delta[RP][4];
+            T dlocal[REGACC ? 1 : RP][4];
+            T(&delta)[RP][4] = *reinterpret_cast<T(*)[RP][4]>(REGACC ? (void*)accr : (void*)dlocal);
+            if (!REGACC) {
 #pragma unroll
-            for (int q = 0; q < RP; q++)
+                for (int q = 0; q < RP; q++)
 #pragma unroll
-                for (int e = 0; e < 4; e++) delta[q][e] = 0;
+                    for (int e = 0; e < 4; e++) delta[q][e] = 0;
+            }
             for (int ub = 0; ub < NB; ub++, t++) {
                 if (!DALL) digits_phase<T, R, 1>(src, abar, n, i, dbuf, ub / l, ub % l, l, a.bg_bits);
                 if (DOUBLE) {
@@ -281,13 +333,27 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
                 } else {
                     KEY_LOAD(kbase + ((size_t)i * NB + ub) * KU);
                     KEY_STORE(kbuf);
+                    __syncthreads();
                 }
-                __syncthreads();
+                // (double-buffered: the slot read below was stored before the
+                // previous block's closing barrier)
                 const uint8_t* kslot = kbuf + (DOUBLE ? (size_t)(t & 1) * KSLOT : 0);
                 const int8_t* dblk = dbuf + (DALL ? (size_t)ub * R * 1024 : 0);
                 mfma_block<T, R, RP>(kslot, dblk, v, jr, pass, delta);
                 if (DOUBLE) KEY_STORE(kbuf + (size_t)((t + 1) & 1) * KSLOT);
                 __syncthreads();
+            }
+            if (REGACC) {
+                T* pd = dst + rbase;
+                __asm__ volatile("" : "+v"(pd));
+#pragma unroll
+                for (int q = 0; q < RP; q++) {
+                    vec4 o;
+#pragma unroll
+                    for (int e = 0; e < 4; e++) o[e] = delta[q][e];
+                    *(vec4*)(pd + q * STEP4) = o;
+                }
+                continue;
             }
             // dst rows of this pass = src rows + delta (16-byte accesses; all
             // loads issued before the stores).  Row tile J = jr + 4a holds
