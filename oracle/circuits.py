@@ -21,7 +21,13 @@ Readings of points the paper leaves open (each listed in the design doc):
 * a > c is c < a; BETWEEN lo AND hi is NOR(a < lo, hi < a);
 * select: AND(mask, v_j) per bit (If-Then-Else with an encrypted zero);
 * SUM: pairwise adder tree in row order, ripple-carry adders whose carry-out
-  becomes the new top bit; an odd operand is zero-extended by one FALSE bit.
+  becomes the new top bit; an odd operand is zero-extended by one FALSE bit;
+* expression trees (the Homomorphic Expression Tree of Section 4.3 B): NOT is
+  the exact negation of a ciphertext (no bootstrap); a != b, a <= b, a >= b
+  are NOT(a == b), NOT(b < a), NOT(a < b); a plaintext constant is its
+  trivial encryption (0, +-1/8) per bit; If-Then-Else(c, x, y) per bit is
+  AND(c, x) + ANDNY(c, y) + 1/8 (a linear step: the two terms are never both
+  TRUE); max(a, b) = ITE(a < b, b, a) and min(a, b) = ITE(a < b, a, b).
 """
 from __future__ import annotations
 
@@ -61,6 +67,14 @@ class PlainBackend:
     def neg(self, x):
         return not x
 
+    def lin(self, xs, weights, c8):
+        """Linear step on bits (+-1 in units of 1/8); the result must again
+        be a valid bit encoding."""
+        v = c8 + sum(w * (1 if x else -1) for w, x in zip(weights, xs))
+        if v not in (-1, 1):
+            raise ValueError(f"linear step leaves the bit encoding: {v}/8")
+        return v == 1
+
 
 class CipherBackend:
     """Bootstrapped gates on LWE ciphertexts (uint64 arrays of n+1 words)."""
@@ -87,6 +101,10 @@ class CipherBackend:
     def neg(self, x):
         out = (np.uint64(0) - np.asarray(x, dtype=np.uint64))
         return out & np.uint64(qmask(self.p.q))
+
+    def lin(self, xs, weights, c8):
+        const = (c8 * (1 << (self.p.q - 3))) & qmask(self.p.q)
+        return lincomb(self.p, np.stack(xs), list(weights), const)
 
 
 def eq(be, a, c):
@@ -148,6 +166,124 @@ def sum_tree(be, operands):
             nxt.append(level[-1] + [be.FALSE])
         level = nxt
     return level[0]
+
+
+# ---------------------------------------------------------- expression trees
+#
+# A WHERE expression (Section 4.3 B) is given as a list of nodes in
+# topological order (every operand index smaller than the node's own); the
+# last node is the root.  Node dicts:
+#   {"kind": "column", "col": i}           value: encrypted column i
+#   {"kind": "const", "value": v}          value: plaintext v (trivial encryption)
+#   {"kind": "literal", "lit": i}          value: encrypted literal i
+#   {"kind": "cmp", "op": o, "a": i, "b": j}   bool, o in eq ne lt le gt ge
+#   {"kind": "and" | "or" | "xor", "a": i, "b": j}   bool
+#   {"kind": "not", "a": i}                bool
+#   {"kind": "max" | "min", "a": i, "b": j}   value
+#   {"kind": "ite", "c": k, "a": i, "b": j}   value: c ? a : b
+VALUE_KINDS = ("column", "const", "literal", "max", "min", "ite")
+BOOL_KINDS = ("cmp", "and", "or", "xor", "not")
+
+
+def compare(be, op, a, b):
+    if op == "eq": return eq(be, a, b)
+    if op == "ne": return be.neg(eq(be, a, b))
+    if op == "lt": return lt(be, a, b)
+    if op == "gt": return lt(be, b, a)
+    if op == "le": return be.neg(lt(be, b, a))
+    if op == "ge": return be.neg(lt(be, a, b))
+    raise ValueError(op)
+
+
+def mux(be, c, x, y):
+    """c ? x : y on one bit: the AND terms are never both TRUE, so their sum
+    plus 1/8 is again a bit."""
+    return be.lin([be.gate("AND", c, x), be.gate("ANDNY", c, y)], [1, 1], 1)
+
+
+def ite(be, c, x, y):
+    return [mux(be, c, x[j], y[j]) for j in range(len(x))]
+
+
+def expr_eval(be, nodes, cols, literals, w):
+    """Value of the root of `nodes` for one row: a bit for a boolean root, a
+    list of w bits for a value root.  cols[i] and literals[i] are lists of w
+    bits of this backend."""
+    vals, kinds = [], []
+    for k, nd in enumerate(nodes):
+        kind = nd["kind"]
+        ops = [nd[x] for x in ("a", "b", "c") if x in nd]
+        if any(not (0 <= i < k) for i in ops):
+            raise ValueError(f"node {k}: operands must precede the node")
+        if kind == "column":
+            v = list(cols[nd["col"]])
+        elif kind == "const":
+            v = [be.TRUE if (int(nd["value"]) >> j) & 1 else be.FALSE for j in range(w)]
+        elif kind == "literal":
+            v = list(literals[nd["lit"]])
+        elif kind in ("cmp", "max", "min"):
+            if kinds[nd["a"]] != "value" or kinds[nd["b"]] != "value":
+                raise ValueError(f"node {k}: {kind} takes values")
+            a, b = vals[nd["a"]], vals[nd["b"]]
+            if kind == "cmp":
+                v = compare(be, nd["op"], a, b)
+            else:
+                m = lt(be, a, b)
+                v = ite(be, m, b, a) if kind == "max" else ite(be, m, a, b)
+        elif kind in ("and", "or", "xor"):
+            if kinds[nd["a"]] != "bool" or kinds[nd["b"]] != "bool":
+                raise ValueError(f"node {k}: {kind} takes booleans")
+            v = be.gate(kind.upper(), vals[nd["a"]], vals[nd["b"]])
+        elif kind == "not":
+            if kinds[nd["a"]] != "bool":
+                raise ValueError(f"node {k}: not takes a boolean")
+            v = be.neg(vals[nd["a"]])
+        elif kind == "ite":
+            if kinds[nd["c"]] != "bool" or kinds[nd["a"]] != "value" or kinds[nd["b"]] != "value":
+                raise ValueError(f"node {k}: ite takes a boolean and two values")
+            v = ite(be, vals[nd["c"]], vals[nd["a"]], vals[nd["b"]])
+        else:
+            raise ValueError(f"node {k}: unknown kind {kind}")
+        vals.append(v)
+        kinds.append("value" if kind in VALUE_KINDS else "bool")
+    return vals[-1]
+
+
+def expr_plain(nodes, cols, literals, w):
+    """Integer semantics of an expression tree (the pin of expr_eval)."""
+    mask = (1 << w) - 1
+    vals = []
+    for nd in nodes:
+        kind = nd["kind"]
+        if kind == "column": v = cols[nd["col"]] & mask
+        elif kind == "const": v = int(nd["value"]) & mask
+        elif kind == "literal": v = literals[nd["lit"]] & mask
+        elif kind == "cmp":
+            a, b = vals[nd["a"]], vals[nd["b"]]
+            v = {"eq": a == b, "ne": a != b, "lt": a < b, "le": a <= b, "gt": a > b, "ge": a >= b}[nd["op"]]
+        elif kind == "and": v = vals[nd["a"]] and vals[nd["b"]]
+        elif kind == "or": v = vals[nd["a"]] or vals[nd["b"]]
+        elif kind == "xor": v = vals[nd["a"]] != vals[nd["b"]]
+        elif kind == "not": v = not vals[nd["a"]]
+        elif kind == "max": v = max(vals[nd["a"]], vals[nd["b"]])
+        elif kind == "min": v = min(vals[nd["a"]], vals[nd["b"]])
+        elif kind == "ite": v = vals[nd["a"]] if vals[nd["c"]] else vals[nd["b"]]
+        else: raise ValueError(kind)
+        vals.append(v)
+    return vals[-1]
+
+
+def expr_rows(p, keys, nodes, col_cts, lit_cts, w, threads=None):
+    """Oracle evaluation of an expression tree for every row.
+    col_cts: list of [rows][w][n+1] arrays; lit_cts: list of [w][n+1] arrays.
+    Returns [rows][n+1] (boolean root) or [rows][w][n+1] (value root)."""
+    rows = len(col_cts[0]) if col_cts else 1
+
+    def one(r):
+        be = CipherBackend(p, keys)
+        out = expr_eval(be, nodes, [list(c[r]) for c in col_cts], [list(x) for x in lit_cts], w)
+        return np.stack(out) if isinstance(out, list) else np.asarray(out, dtype=np.uint64)
+    return np.stack(parallel_map(one, range(rows), threads))
 
 
 # ------------------------------------------------------------------ drivers

@@ -45,6 +45,7 @@ TAG_CT_NOISE = 8
 TAG_DATA = 9
 TAG_LITERAL = 10
 TAG_SHAPE = 11
+TAG_EXPR = 12
 
 
 def mix64_int(z: int) -> int:
@@ -260,3 +261,88 @@ def uneven_tables(seed: int, count: int = 16, lo: int = 100, hi: int = 65536):
     rows = log_uniform_int(seed, TAG_SHAPE, count, lo, hi)
     ops = (uniform_ints(seed, TAG_SHAPE, count, 16, start=count) % np.uint64(3)).astype(np.int64)
     return rows, ops
+
+
+CMP_NAMES = ("eq", "ne", "lt", "le", "gt", "ge")
+
+
+def paper_where_example(age_col: int = 0, salary_col: int = 1, age_lit=18, salary_lit=1000):
+    """Node list of the WHERE clause used as the expression-tree example of
+    Section 4.3 B (age > 18 AND salary < 1000); the two numbers become
+    plaintext constants."""
+    return [
+        {"kind": "column", "col": age_col},
+        {"kind": "const", "value": age_lit},
+        {"kind": "cmp", "op": "gt", "a": 0, "b": 1},
+        {"kind": "column", "col": salary_col},
+        {"kind": "const", "value": salary_lit},
+        {"kind": "cmp", "op": "lt", "a": 3, "b": 4},
+        {"kind": "and", "a": 2, "b": 5},
+    ]
+
+
+def random_expr(seed: int, ncols: int, nlits: int, w: int, depth: int = 3, root: str = "bool"):
+    """A seeded random expression tree as a topologically ordered node list
+    (operands precede their node; the last node is the root).  Boolean nodes
+    draw from cmp/and/or/xor/not, value nodes from column/const/literal/
+    max/min/ite; an operand is sometimes an earlier node of the same kind, so
+    the result is a DAG with shared subexpressions."""
+    draws = raw(seed, TAG_EXPR, 4096)
+    pos = [0]
+
+    def pick(n):
+        v = int(draws[pos[0] % draws.size]) % n
+        pos[0] += 1
+        return v
+
+    nodes, kinds = [], []
+
+    def emit(nd, kind):
+        nodes.append(nd)
+        kinds.append(kind)
+        return len(nodes) - 1
+
+    def reuse(kind):
+        cand = [i for i, k in enumerate(kinds) if k == kind]
+        if cand and pick(4) == 0:
+            return cand[pick(len(cand))]
+        return None
+
+    def value(d):
+        r = reuse("value")
+        if r is not None:
+            return r
+        leaf = d <= 0 or pick(3) != 0
+        if leaf:
+            t = pick(3 if nlits else 2)
+            if t == 0:
+                return emit({"kind": "column", "col": pick(ncols)}, "value")
+            if t == 1:
+                return emit({"kind": "const", "value": pick(1 << w)}, "value")
+            return emit({"kind": "literal", "lit": pick(nlits)}, "value")
+        t = pick(3)
+        if t < 2:
+            a, b = value(d - 1), value(d - 1)
+            return emit({"kind": ("max", "min")[t], "a": a, "b": b}, "value")
+        c = boolean(d - 1)
+        a, b = value(d - 1), value(d - 1)
+        return emit({"kind": "ite", "c": c, "a": a, "b": b}, "value")
+
+    def boolean(d):
+        r = reuse("bool")
+        if r is not None:
+            return r
+        t = 0 if d <= 0 else pick(5)
+        if t == 0:
+            a, b = value(d - 1), value(d - 1)
+            return emit({"kind": "cmp", "op": CMP_NAMES[pick(6)], "a": a, "b": b}, "bool")
+        if t == 4:
+            return emit({"kind": "not", "a": boolean(d - 1)}, "bool")
+        a, b = boolean(d - 1), boolean(d - 1)
+        return emit({"kind": ("and", "or", "xor")[t - 1], "a": a, "b": b}, "bool")
+
+    if root == "bool":
+        boolean(depth)
+    else:
+        value(depth)
+    return nodes
