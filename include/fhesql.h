@@ -166,6 +166,59 @@ typedef struct sql_table_query {
 int sql_scan_batch(tfhe_ctx* ctx, const sql_table_query* q, uint32_t count, int use_graph,
                    void* hip_stream);
 
+/* ---- Homomorphic expression trees (Section 4.3 B: leaves are operands,
+ * inner nodes are operators given as plaintext metadata).
+ *
+ * Value nodes are w-bit integers (bit-wise encrypted, LSB first); boolean
+ * nodes are single encrypted bits.  Circuits, per row:
+ *   EQ: XNOR per bit + balanced AND tree; LT: borrow chain
+ *   b_j = MAJ(not a_j, c_j, b_{j-1}), b_{-1} = FALSE; GT(a,b) = LT(b,a);
+ *   NE = NOT EQ; LE(a,b) = NOT LT(b,a); GE(a,b) = NOT LT(a,b);
+ *   AND, OR, XOR: one bootstrapped gate; NOT: exact negation (no bootstrap);
+ *   ITE(c, x, y) per bit: AND(c, x_j) + ANDNY(c, y_j) + 1/8 (linear, exact);
+ *   MAX(a,b) = ITE(LT(a,b), b, a); MIN(a,b) = ITE(LT(a,b), a, b);
+ *   CONST: the trivial encryption (0, +-1/8) of each bit of `value`. */
+#define SQL_EXPR_COLUMN 0   /* value: column `col` of d_cols */
+#define SQL_EXPR_CONST 1    /* value: plaintext `value` (low w bits) */
+#define SQL_EXPR_LITERAL 2  /* value: encrypted literal at d_lit, [w][n+1] */
+#define SQL_EXPR_CMP 3      /* bool: `op` (SQL_CMP_*) of values a, b */
+#define SQL_EXPR_AND 4      /* bool: a AND b */
+#define SQL_EXPR_OR 5       /* bool: a OR b */
+#define SQL_EXPR_XOR 6      /* bool: a XOR b */
+#define SQL_EXPR_NOT 7      /* bool: NOT a */
+#define SQL_EXPR_MAX 8      /* value: max(a, b) */
+#define SQL_EXPR_MIN 9      /* value: min(a, b) */
+#define SQL_EXPR_ITE 10     /* value: c ? a : b (c bool) */
+
+#define SQL_CMP_EQ 0
+#define SQL_CMP_NE 1
+#define SQL_CMP_LT 2
+#define SQL_CMP_LE 3
+#define SQL_CMP_GT 4
+#define SQL_CMP_GE 5
+
+typedef struct sql_expr {
+    int32_t kind;         /* SQL_EXPR_* */
+    int32_t op;           /* SQL_EXPR_CMP: SQL_CMP_* */
+    int32_t a, b, c;      /* operand node indices, each smaller than this node's */
+    int32_t col;          /* SQL_EXPR_COLUMN: index into d_cols */
+    uint64_t value;       /* SQL_EXPR_CONST */
+    const void* d_lit;    /* SQL_EXPR_LITERAL: device [w][n+1] */
+} sql_expr;
+
+/* Evaluates nodes[0..nnodes-1] (topological order; the last node is the root)
+ * for every row.  d_cols: host array of ncols device pointers, each
+ * [rows][w][n+1].  d_out: [rows][n+1] for a boolean root, [rows][w][n+1] for
+ * a value root; it must not alias an input.  Every gate of the netlist is
+ * bootstrapped whatever its inputs (no constant folding), so the output bits
+ * are a function of the node list and the inputs alone.  Errors: TFHE_EINVAL
+ * for an unknown kind or operator, an operand index out of order, a boolean
+ * where a value is expected (or the reverse), a column index >= ncols or a
+ * null pointer; TFHE_ESHAPE for w outside 1..64. */
+int sql_expr_eval(tfhe_ctx* ctx, const void* const* d_cols, uint32_t ncols, uint32_t rows,
+                  uint32_t w, const sql_expr* nodes, uint32_t nnodes, void* d_out,
+                  void* hip_stream);
+
 /* Kernel timing.  While enabled (on != 0), every blind-rotation and
  * key-switching kernel launched by this context is bracketed by HIP events
  * recorded on the stream it runs on (not during graph capture).  Enabling

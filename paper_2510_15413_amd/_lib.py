@@ -34,8 +34,12 @@ EXPORTS = [
     "tfhe_lwe_encrypt", "tfhe_lwe_phase", "tfhe_timing_enable", "tfhe_timing_read",
     "tfhe_set_tuning", "sql_server_create", "sql_server_destroy", "sql_server_submit",
     "sql_server_step", "sql_server_done", "sql_server_bytes_in_use",
-    "sql_radix_mask_scan", "sql_radix_masked_select", "sql_radix_sum",
+    "sql_radix_mask_scan", "sql_radix_masked_select", "sql_radix_sum", "sql_expr_eval",
 ]
+# Expression-tree node kinds and comparison operators (sql_expr).
+SQL_EXPR_KINDS = {"column": 0, "const": 1, "literal": 2, "cmp": 3, "and": 4, "or": 5, "xor": 6, "not": 7,
+                  "max": 8, "min": 9, "ite": 10}
+SQL_CMP_OPS = {"eq": 0, "ne": 1, "lt": 2, "le": 3, "gt": 4, "ge": 5}
 TFHE_TUNE_MAX_BATCH = 1
 TFHE_TUNE_ROW_PASS = 2
 TFHE_TUNE_DIGIT_BLOCKS = 3
@@ -61,6 +65,12 @@ class SqlTableQuery(ctypes.Structure):
     _fields_ = [("d_col", ctypes.c_void_p), ("d_sel_col", ctypes.c_void_p), ("rows", ctypes.c_uint32),
                 ("w", ctypes.c_uint32), ("op", ctypes.c_int), ("d_lit_a", ctypes.c_void_p),
                 ("d_lit_b", ctypes.c_void_p), ("d_mask", ctypes.c_void_p), ("d_sel_out", ctypes.c_void_p)]
+
+
+class SqlExpr(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("op", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32),
+                ("c", ctypes.c_int32), ("col", ctypes.c_int32), ("value", ctypes.c_uint64),
+                ("d_lit", ctypes.c_void_p)]
 
 
 _lib = None
@@ -106,6 +116,7 @@ def load():
         "sql_radix_mask_scan": (i32, [vp, vp, u32, u32, i32, vp, vp, vp]),
         "sql_radix_masked_select": (i32, [vp, vp, vp, u32, u32, vp, vp]),
         "sql_radix_sum": (i32, [vp, vp, u32, u32, vp, vp]),
+        "sql_expr_eval": (i32, [vp, ctypes.POINTER(vp), u32, u32, u32, ctypes.POINTER(SqlExpr), u32, vp, vp]),
         "tfhe_timing_read": (i32, [vp, i32, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(u64)]),
     }
@@ -273,6 +284,33 @@ class Context:
         for t, nm in ((vals, "vals"), (out, "out")):
             _check_dev(t, nm)
         self._rc(load().sql_radix_sum(self._h, _ptr(vals), rows, nb, _ptr(out), _stream(stream)), "sql_radix_sum")
+
+    def sql_expr_eval(self, nodes, cols, rows, w, out, lits=(), stream=None):
+        """Evaluate an expression tree for every row.  nodes: list of dicts
+        {"kind": column|const|literal|cmp|and|or|xor|not|max|min|ite, "col",
+        "value", "lit" (index into lits), "op" (eq ne lt le gt ge), "a", "b",
+        "c"}; cols, lits: device tensors [rows][w][n+1] and [w][n+1]; out:
+        [rows][n+1] (boolean root) or [rows][w][n+1] (value root)."""
+        for i, t in enumerate(cols):
+            _check_dev(t, f"cols[{i}]")
+        for i, t in enumerate(lits):
+            _check_dev(t, f"lits[{i}]")
+        _check_dev(out, "out")
+        arr = (SqlExpr * max(1, len(nodes)))()
+        for i, nd in enumerate(nodes):
+            kind = nd["kind"]
+            e = SqlExpr()
+            e.kind = SQL_EXPR_KINDS.get(kind, -1) if isinstance(kind, str) else int(kind)
+            e.op = SQL_CMP_OPS.get(nd.get("op"), -1) if isinstance(nd.get("op"), str) else int(nd.get("op", 0))
+            e.a, e.b, e.c = int(nd.get("a", -1)), int(nd.get("b", -1)), int(nd.get("c", -1))
+            e.col = int(nd.get("col", -1))
+            e.value = int(nd.get("value", 0)) & 0xFFFFFFFFFFFFFFFF
+            if kind == "literal":
+                e.d_lit = lits[nd["lit"]].data_ptr()
+            arr[i] = e
+        colp = (ctypes.c_void_p * max(1, len(cols)))(*[t.data_ptr() for t in cols])
+        self._rc(load().sql_expr_eval(self._h, colp, len(cols), rows, w, arr, len(nodes), _ptr(out),
+                                      _stream(stream)), "sql_expr_eval")
 
     def sql_scan_batch(self, queries, use_graph=False, stream=None):
         """queries: list of dicts with col, rows, w, op, lit_a, lit_b, mask, sel_col, sel_out."""

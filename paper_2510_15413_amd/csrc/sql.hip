@@ -17,6 +17,7 @@
 // gates of every segment: linear combination, blind rotation + sample
 // extraction (MFMA or plain), key switching into the gate outputs.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 
 #include "fhesql_internal.h"
@@ -72,6 +73,50 @@ int launch_combine(tfhe_ctx* c, const Segment* d_segs, const uint32_t* d_start, 
     return hip_check(c, hipGetLastError(), "launch combine");
 }
 
+// Linear steps without a bootstrap (exact negation, the If-Then-Else sum,
+// copies of an expression's result): out[r] = cst*e_n + sum_j w_j in_j[r],
+// written straight to each segment's output rows.
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void lin_kernel(const Segment* __restrict__ segs, const uint32_t* __restrict__ start,
+                                                  int nseg, uint32_t total, int n) {
+    const uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= total) return;
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    const Segment& sg = segs[lo];
+    const int64_t r = (int64_t)(g - start[lo]);
+    const T* in0 = (const T*)(uintptr_t)sg.in[0] + r * sg.in_stride[0];
+    const T* in1 = (const T*)(uintptr_t)sg.in[1] + r * sg.in_stride[1];
+    const T* in2 = (const T*)(uintptr_t)sg.in[2] + r * sg.in_stride[2];
+    const T w0 = (T)(int64_t)sg.w[0], w1 = (T)(int64_t)sg.w[1], w2 = (T)(int64_t)sg.w[2];
+    T* o = (T*)(uintptr_t)sg.out + r * sg.out_stride;
+    for (int w = lane; w <= n; w += 64) {
+        T acc = w == n ? (T)sg.cst : (T)0;
+        if (sg.nin > 0) acc += w0 * in0[w];
+        if (sg.nin > 1) acc += w1 * in1[w];
+        if (sg.nin > 2) acc += w2 * in2[w];
+        o[w] = acc;
+    }
+}
+
+int launch_lin(tfhe_ctx* c, const Segment* d_segs, const uint32_t* d_start, int nseg, uint32_t total, hipStream_t s) {
+    if (!total) return TFHE_OK;
+    const unsigned grid = (total + 3) / 4;
+    if (c->q == 32)
+        hipLaunchKernelGGL(lin_kernel<uint32_t>, dim3(grid), dim3(256), 0, s, d_segs, d_start, nseg, total, (int)c->p.n);
+    else
+        hipLaunchKernelGGL(lin_kernel<uint64_t>, dim3(grid), dim3(256), 0, s, d_segs, d_start, nseg, total, (int)c->p.n);
+    return hip_check(c, hipGetLastError(), "launch lin");
+}
+
+}  // namespace
+
 // ------------------------------------------------------------- netlists
 
 namespace {
@@ -86,8 +131,9 @@ struct Copy {  // device-to-device copy done before a level's gates
 };
 
 struct Level {
-    std::vector<Segment> segs;
-    std::vector<Copy> copies;
+    std::vector<Segment> segs;    // bootstrapped gates
+    std::vector<Copy> copies;     // run first
+    std::vector<Segment> lins;    // linear steps, run after the copies, before the gates
 };
 
 struct Netlist {
@@ -121,6 +167,10 @@ struct Builder {
     void level_push(size_t lev, const Segment& s) {
         if (net.levels.size() <= lev) net.levels.resize(lev + 1);
         net.levels[lev].segs.push_back(s);
+    }
+    void lin_push(size_t lev, const Segment& s) {
+        if (net.levels.size() <= lev) net.levels.resize(lev + 1);
+        net.levels[lev].lins.push_back(s);
     }
     void copy_push(size_t lev, uint64_t src, uint64_t dst, uint64_t bytes) {
         if (net.levels.size() <= lev) net.levels.resize(lev + 1);
@@ -385,6 +435,141 @@ struct Builder {
     }
 };
 
+// ---------------------------------------------------- expression trees
+
+// A wire is one encrypted bit for every row: a ciphertext reference whose
+// sign carries folded NOTs (w * (-x) = (-w) * x exactly mod 2^q), or a
+// plaintext constant (its trivial encryption (0, +-1/8) folded into the
+// consuming step's constant).  rg / rl: first level whose gates / linear
+// steps may read the wire (a linear step's output is read by the gates of its
+// own level, by linear steps only from the next level on).
+struct Wire {
+    bool is_const = false;
+    bool val = false;
+    Ref r{};
+    int sign = 1;
+    size_t rg = 0, rl = 0;
+};
+
+struct ExprVal {
+    bool is_bool = false;
+    std::vector<Wire> bits;  // 1 for a boolean, w for a value
+};
+
+struct ExprCompiler {
+    Builder& b;
+    uint32_t rows;
+
+    static Wire constant(bool v) {
+        Wire x;
+        x.is_const = true;
+        x.val = v;
+        return x;
+    }
+    static Wire neg(Wire x) {
+        if (x.is_const) x.val = !x.val;
+        else x.sign = -x.sign;
+        return x;
+    }
+    // Fills a segment's operands from (wire, weight) pairs; returns the
+    // constant in units of 1/8 after folding constant wires.
+    static int64_t operands(Segment& s, const std::vector<std::pair<const Wire*, int>>& ins, int64_t cst8) {
+        int k = 0;
+        for (auto& pr : ins) {
+            const Wire& x = *pr.first;
+            if (x.is_const) { cst8 += x.val ? pr.second : -pr.second; continue; }
+            s.in[k] = x.r.addr;
+            s.in_stride[k] = x.r.stride;
+            s.w[k] = pr.second * x.sign;
+            k++;
+        }
+        s.nin = k;
+        return cst8;
+    }
+    // Bootstrapped gate; placed at the first level where every operand exists.
+    Wire gate(int op, std::vector<const Wire*> ins) {
+        const GateForm f = gate_form(op);
+        size_t lev = 0;
+        std::vector<std::pair<const Wire*, int>> wi;
+        for (int j = 0; j < f.nin; j++) {
+            if (!ins[j]->is_const) lev = std::max(lev, ins[j]->rg);
+            wi.push_back({ins[j], f.w[j]});
+        }
+        Segment s{};
+        const int64_t cst8 = operands(s, wi, f.c8);
+        Wire o;
+        o.r = b.tmp(rows);
+        s.cst = b.wrap(cst8 * (int64_t)b.eighth());
+        s.out = o.r.addr;
+        s.out_stride = o.r.stride;
+        s.rows = rows;
+        s.lut = -1;
+        b.level_push(lev, s);
+        o.rg = o.rl = lev + 1;
+        return o;
+    }
+    // Linear step (no bootstrap) into `out` (a fresh temporary when null).
+    Wire lin(const std::vector<std::pair<const Wire*, int>>& ins, int64_t cst8, const Ref* out) {
+        size_t lev = 0;
+        for (auto& pr : ins)
+            if (!pr.first->is_const) lev = std::max(lev, pr.first->rl);
+        Segment s{};
+        cst8 = operands(s, ins, cst8);
+        Wire o;
+        o.r = out ? *out : b.tmp(rows);
+        s.cst = b.wrap(cst8 * (int64_t)b.eighth());
+        s.out = o.r.addr;
+        s.out_stride = o.r.stride;
+        s.rows = rows;
+        s.lut = -1;
+        b.lin_push(lev, s);
+        o.rg = lev;
+        o.rl = lev + 1;
+        return o;
+    }
+
+    Wire eq(const ExprVal& a, const ExprVal& c) {
+        std::vector<Wire> xs;
+        for (size_t j = 0; j < a.bits.size(); j++) xs.push_back(gate(G_XNOR, {&a.bits[j], &c.bits[j]}));
+        while (xs.size() > 1) {  // pairs (0,1),(2,3),...; an odd last element passes up
+            std::vector<Wire> nxt;
+            for (size_t i = 0; i + 1 < xs.size(); i += 2) nxt.push_back(gate(G_AND, {&xs[i], &xs[i + 1]}));
+            if (xs.size() % 2) nxt.push_back(xs.back());
+            xs.swap(nxt);
+        }
+        return xs[0];
+    }
+    Wire lt(const ExprVal& a, const ExprVal& c) {  // borrow chain, b_{-1} = FALSE
+        Wire bw = constant(false);
+        for (size_t j = 0; j < a.bits.size(); j++) {
+            const Wire na = neg(a.bits[j]);
+            bw = gate(G_MAJ, {&na, &c.bits[j], &bw});
+        }
+        return bw;
+    }
+    Wire compare(int op, const ExprVal& a, const ExprVal& c) {
+        switch (op) {
+            case SQL_CMP_EQ: return eq(a, c);
+            case SQL_CMP_NE: return neg(eq(a, c));
+            case SQL_CMP_LT: return lt(a, c);
+            case SQL_CMP_GT: return lt(c, a);
+            case SQL_CMP_LE: return neg(lt(c, a));
+            default: return neg(lt(a, c));  // SQL_CMP_GE
+        }
+    }
+    // c ? x : y per bit: AND(c, x) + ANDNY(c, y) + 1/8 (never both TRUE).
+    ExprVal ite(const Wire& cw, const ExprVal& x, const ExprVal& y) {
+        ExprVal o;
+        for (size_t j = 0; j < x.bits.size(); j++) {
+            const Wire u1 = gate(G_AND, {&cw, &x.bits[j]});
+            const Wire u2 = gate(G_ANDNY, {&cw, &y.bits[j]});
+            o.bits.push_back(lin({{&u1, 1}, {&u2, 1}}, 1, nullptr));
+        }
+        return o;
+    }
+};
+
+// ---------------------------------------------------------- execution
 // ---------------------------------------------------------- execution
 
 struct Exec {
@@ -406,7 +591,7 @@ struct Exec {
             nseg_total += lv.segs.size();
         }
         size_t ncopies = 0;
-        for (auto& lv : net.levels) ncopies += lv.copies.size();
+        for (auto& lv : net.levels) ncopies += lv.copies.size() + lv.lins.size();
         if (!max_gates && !ncopies) return TFHE_OK;
         const uint32_t chunk = (uint32_t)std::max<size_t>(1, std::min<size_t>(max_gates, max_batch));
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -419,20 +604,33 @@ struct Exec {
         // segments split into chunks: upper bound of pieces
         std::vector<Segment> flat;
         std::vector<uint32_t> starts;
-        struct Piece { size_t seg_off; int nseg; uint32_t total; size_t copy_off; int ncopy; };
+        // A level's first piece also carries its copies and linear steps.
+        struct Piece {
+            size_t seg_off; int nseg; uint32_t total; size_t copy_off; int ncopy;
+            size_t lin_off; int nlin; uint32_t lin_total;
+        };
         std::vector<Piece> pieces;
         std::vector<Copy> copies;
         for (auto& L : net.levels) {
             auto& lv = L.segs;
             const size_t c0 = copies.size();
             copies.insert(copies.end(), L.copies.begin(), L.copies.end());
+            const size_t l0 = flat.size();
+            uint32_t lin_total = 0;
+            for (const Segment& sg : L.lins) {
+                flat.push_back(sg);
+                starts.push_back(lin_total);
+                lin_total += sg.rows;
+            }
             bool first = true;
             // split the level into chunks of at most `chunk` gates
             size_t i = 0;
             uint32_t carried = 0;  // rows of segment i already emitted
-            if (lv.empty() && !L.copies.empty()) pieces.push_back(Piece{flat.size(), 0, 0, c0, (int)L.copies.size()});
+            if (lv.empty() && (!L.copies.empty() || lin_total))
+                pieces.push_back(Piece{flat.size(), 0, 0, c0, (int)L.copies.size(), l0, (int)L.lins.size(), lin_total});
             while (i < lv.size()) {
-                Piece pc{flat.size(), 0, 0, c0, first ? (int)L.copies.size() : 0};
+                Piece pc{flat.size(), 0, 0, c0, first ? (int)L.copies.size() : 0,
+                         l0, first ? (int)L.lins.size() : 0, first ? lin_total : 0u};
                 first = false;
                 while (i < lv.size() && pc.total < chunk) {
                     Segment sg = lv[i];
@@ -497,6 +695,7 @@ struct Exec {
                                                  hipMemcpyDeviceToDevice, rs), "level copy");
             }
             if (rc) break;
+            if (pc.nlin && (rc = launch_lin(c, dsegs + pc.lin_off, dstart + pc.lin_off, pc.nlin, pc.lin_total, rs))) break;
             if (!pc.total) continue;
             if ((rc = launch_combine(c, dsegs + pc.seg_off, dstart + pc.seg_off, pc.nseg, pc.total, lwe, ptrs, tvi, rs))) break;
             if ((rc = launch_blind_rotate(c, lwe, net.lut_table, net.lut_table ? tvi : nullptr, big, pc.total,
@@ -608,6 +807,90 @@ extern "C" int sql_masked_sum(tfhe_ctx* c, const void* d_mask, const void* d_col
     const size_t lw = b.lw;
     b.masked_sum(0, rows, w, dev(d_mask, lw), dev(d_col, (size_t)w * lw), (uint64_t)(uintptr_t)d_sum,
                  (uint64_t)(uintptr_t)c->d_false);
+    Exec ex(c, (hipStream_t)stream);
+    return ex.run(b.net, false);
+}
+
+// Homomorphic expression tree (Section 4.3 B) over a table's columns.
+extern "C" int sql_expr_eval(tfhe_ctx* c, const void* const* d_cols, uint32_t ncols, uint32_t rows, uint32_t w,
+                             const sql_expr* nodes, uint32_t nnodes, void* d_out, void* stream) {
+    if (!c) return TFHE_EINVAL;
+    if (!nodes || !nnodes) return ctx_fail(c, TFHE_EINVAL, "empty expression");
+    if (w < 1 || w > 64) return ctx_fail(c, TFHE_ESHAPE, "value width must be 1..64 bits");
+    if (!d_out) return ctx_fail(c, TFHE_EINVAL, "null output pointer");
+    if (ncols && !d_cols) return ctx_fail(c, TFHE_EINVAL, "null column array");
+    // type check: every operand precedes its node and has the expected kind
+    std::vector<char> isb(nnodes, 0);
+    for (uint32_t k = 0; k < nnodes; k++) {
+        const sql_expr& e = nodes[k];
+        auto opnd = [&](int32_t i, bool want_bool) {
+            return i >= 0 && (uint32_t)i < k && (isb[i] != 0) == want_bool;
+        };
+        bool ok = true;
+        switch (e.kind) {
+            case SQL_EXPR_COLUMN: ok = e.col >= 0 && (uint32_t)e.col < ncols && d_cols[e.col]; break;
+            case SQL_EXPR_CONST: break;
+            case SQL_EXPR_LITERAL: ok = e.d_lit != nullptr; break;
+            case SQL_EXPR_CMP: ok = e.op >= SQL_CMP_EQ && e.op <= SQL_CMP_GE && opnd(e.a, false) && opnd(e.b, false); break;
+            case SQL_EXPR_AND: case SQL_EXPR_OR: case SQL_EXPR_XOR: ok = opnd(e.a, true) && opnd(e.b, true); break;
+            case SQL_EXPR_NOT: ok = opnd(e.a, true); break;
+            case SQL_EXPR_MAX: case SQL_EXPR_MIN: ok = opnd(e.a, false) && opnd(e.b, false); break;
+            case SQL_EXPR_ITE: ok = opnd(e.c, true) && opnd(e.a, false) && opnd(e.b, false); break;
+            default: ok = false;
+        }
+        if (!ok) {
+            char msg[96];
+            snprintf(msg, sizeof msg, "expression node %u: bad kind, operator, operand or pointer", k);
+            return ctx_fail(c, TFHE_EINVAL, msg);
+        }
+        isb[k] = e.kind == SQL_EXPR_CMP || e.kind == SQL_EXPR_AND || e.kind == SQL_EXPR_OR ||
+                 e.kind == SQL_EXPR_XOR || e.kind == SQL_EXPR_NOT;
+    }
+    if (!rows) return TFHE_OK;
+    Builder b(c);
+    ExprCompiler ec{b, rows};
+    const size_t lw = b.lw, wb = b.wb;
+    std::vector<ExprVal> v(nnodes);
+    for (uint32_t k = 0; k < nnodes; k++) {
+        const sql_expr& e = nodes[k];
+        ExprVal& o = v[k];
+        o.is_bool = isb[k] != 0;
+        switch (e.kind) {
+            case SQL_EXPR_COLUMN:
+            case SQL_EXPR_LITERAL: {
+                const Ref base = e.kind == SQL_EXPR_COLUMN ? dev(d_cols[e.col], (size_t)w * lw) : dev(e.d_lit, 0);
+                for (uint32_t j = 0; j < w; j++) {
+                    Wire x;
+                    x.r = Builder::bit(base, j, lw, wb);
+                    o.bits.push_back(x);
+                }
+                break;
+            }
+            case SQL_EXPR_CONST:
+                for (uint32_t j = 0; j < w; j++) o.bits.push_back(ExprCompiler::constant((e.value >> j) & 1));
+                break;
+            case SQL_EXPR_CMP: o.bits.push_back(ec.compare(e.op, v[e.a], v[e.b])); break;
+            case SQL_EXPR_AND: o.bits.push_back(ec.gate(G_AND, {&v[e.a].bits[0], &v[e.b].bits[0]})); break;
+            case SQL_EXPR_OR: o.bits.push_back(ec.gate(G_OR, {&v[e.a].bits[0], &v[e.b].bits[0]})); break;
+            case SQL_EXPR_XOR: o.bits.push_back(ec.gate(G_XOR, {&v[e.a].bits[0], &v[e.b].bits[0]})); break;
+            case SQL_EXPR_NOT: o.bits.push_back(ExprCompiler::neg(v[e.a].bits[0])); break;
+            case SQL_EXPR_MAX:
+            case SQL_EXPR_MIN: {
+                const Wire m = ec.lt(v[e.a], v[e.b]);
+                o.bits = e.kind == SQL_EXPR_MAX ? ec.ite(m, v[e.b], v[e.a]).bits : ec.ite(m, v[e.a], v[e.b]).bits;
+                break;
+            }
+            case SQL_EXPR_ITE: o.bits = ec.ite(v[e.c].bits[0], v[e.a], v[e.b]).bits; break;
+        }
+    }
+    // the root's bits are written to d_out by linear steps (exact copies,
+    // negations or trivial encryptions)
+    const ExprVal& root = v[nnodes - 1];
+    for (size_t j = 0; j < root.bits.size(); j++) {
+        const Ref o = root.is_bool ? dev(d_out, lw)
+                                   : Ref{(uint64_t)(uintptr_t)d_out + (uint64_t)j * lw * wb, (int64_t)((size_t)w * lw)};
+        ec.lin({{&root.bits[j], 1}}, 0, &o);
+    }
     Exec ex(c, (hipStream_t)stream);
     return ex.run(b.net, false);
 }
