@@ -103,8 +103,11 @@ int tfhe_set_kernel(tfhe_ctx* ctx, int kind);
  * Returns TFHE_EINVAL for an unknown key or unsupported value. */
 #define TFHE_TUNE_MAX_BATCH 1
 #define TFHE_TUNE_ROW_PASS 2
-/*   TFHE_TUNE_DIGIT_BLOCKS 0 = form all digit blocks of a CMux step at once when
- *                        they fit in LDS (default), 1 = one (u,p) block at a time. */
+/*   TFHE_TUNE_DIGIT_BLOCKS 0 = the largest digit grouping that fits in LDS
+ *                        (default): all blocks of a CMux step at once, else
+ *                        pairs of levels of one component (l even), else one
+ *                        (u,p) block at a time; 1 = one block at a time;
+ *                        2 = pairs when l is even and they fit, else one. */
 #define TFHE_TUNE_DIGIT_BLOCKS 3
 int tfhe_set_tuning(tfhe_ctx* ctx, int key, int64_t value);
 

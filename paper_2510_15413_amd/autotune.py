@@ -14,7 +14,7 @@ import time
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "fhesql_autotune.json")
 
-ROW_PASS = {(32, 256): [4, 2], (32, 512): [8, 4], (32, 1024): [16, 8], (64, 2048): [4, 8]}
+ROW_PASS = {(32, 256): [4, 2], (32, 512): [8, 4], (32, 1024): [16, 8], (64, 2048): [8, 4]}
 
 
 def candidates(p, batches=(16384, 32768, 65536, 131072, 262144)):

@@ -50,14 +50,15 @@ FHE_DEV size_t acc_idx(int N, int v, int j, int c) {
 // Gadget digits of the rotate-diff X^{abar} ACC_u - ACC_u for 16 cts, written
 // in the MFMA B-fragment layout: block (u*l+p, chunk) of 1 KB, lane (g,c) holds
 // the 16 digits of coefficients 64*chunk + 16*g + 0..15 of ciphertext c.
-// U components starting at u_lo; p_only >= 0 keeps only that level (block 0).
+// U components starting at u_lo, levels p_lo .. p_lo+p_n-1 of each: block
+// (u-u_lo)*p_n + (p-p_lo).  One rotate-diff pass yields all levels formed.
 // A work item is 4 consecutive coefficients of one ciphertext: its own 4
 // words are one 16-byte group of the accumulator layout and the 4 rotated
 // words straddle at most two such groups, so an item takes three vector
 // loads; the loads of G items are issued together.
 template <typename T, int R, int U>
 FHE_DEV void digits_phase(const T* __restrict__ src, const uint16_t* abar, int n, int i,
-                          int8_t* dbuf, int u_lo, int p_only, int l, int bgb) {
+                          int8_t* dbuf, int u_lo, int p_lo, int p_n, int l, int bgb) {
     typedef T vec4 __attribute__((ext_vector_type(4)));
     constexpr int N = R * 64;
     constexpr int NG = N / 4;  // 4-word groups per component
@@ -121,8 +122,7 @@ FHE_DEV void digits_phase(const T* __restrict__ src, const uint16_t* abar, int n
             }
             const int j0 = 4 * kg;
             const int ch = j0 >> 6, g = (j0 >> 4) & 3, bo = j0 & 15;
-            for (int p = 0; p < l; p++) {
-                if (p_only >= 0 && p != p_only) continue;
+            for (int p = p_lo; p < p_lo + p_n; p++) {
                 const int shp = (l - 1 - p) * bgb;
                 uint32_t packed = 0;
 #pragma unroll
@@ -130,7 +130,7 @@ FHE_DEV void digits_phase(const T* __restrict__ src, const uint16_t* abar, int n
                     const int d = (int)((y[e] >> shp) & bgm) - half;
                     packed |= ((uint32_t)(d & 0xFF)) << (8 * e);
                 }
-                const int blk = p_only >= 0 ? 0 : (u * l + p);
+                const int blk = (u - u_lo) * p_n + (p - p_lo);
                 *(uint32_t*)(dbuf + ((size_t)blk * R + ch) * 1024 + (g * 16 + c) * 16 + bo) = packed;
             }
         }
@@ -218,13 +218,17 @@ FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr,
     }
 }
 
-template <typename T, int R, int RP, bool DALL>
+// DG: digit blocks formed per rotate-diff pass -- 0 all (k+1)l blocks of a
+// step up front (key double-buffered), else DG consecutive levels of one
+// component just before their MFMA blocks.
+template <typename T, int R, int RP, int DG>
 __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void br_mfma_kernel(BrArgs a) {
     constexpr int N = R * 64;
     constexpr int NL = Torus<T>::LIMBS;
     constexpr int KSLOT = 2 * NL * 2 * N;  // bytes of one (u,p) key block
     constexpr int KV = (KSLOT / 16 + THREADS - 1) / THREADS;
     constexpr int LG = __builtin_ctz(2 * N);
+    constexpr bool DALL = DG == 0;
     constexpr bool DOUBLE = DALL;
     const int n = a.n, l = a.l, NB = 2 * l;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -235,7 +239,7 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     uint16_t* abar = (uint16_t*)smem;
     size_t off = ((size_t)CTS * n * 2 + 15) & ~(size_t)15;
     int8_t* dbuf = (int8_t*)(smem + off);
-    off += (size_t)(DALL ? NB : 1) * R * 1024;
+    off += (size_t)(DALL ? NB : DG) * R * 1024;
     uint8_t* kbuf = smem + off;
 
     // With all digits of a step formed up front (DALL) the accumulator is
@@ -311,7 +315,7 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     }
     for (int i = 0; i < n; i++) {
         if (DALL) {
-            digits_phase<T, R, 2>(src, abar, n, i, dbuf, 0, -1, l, a.bg_bits);
+            digits_phase<T, R, 2>(src, abar, n, i, dbuf, 0, 0, l, l, a.bg_bits);
             __syncthreads();
         }
         for (int pass = 0; pass < NPASS; pass++) {
@@ -324,7 +328,7 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
                     for (int e = 0; e < 4; e++) delta[q][e] = 0;
             }
             for (int ub = 0; ub < NB; ub++, t++) {
-                if (!DALL) digits_phase<T, R, 1>(src, abar, n, i, dbuf, ub / l, ub % l, l, a.bg_bits);
+                if (!DALL && ub % DG == 0) digits_phase<T, R, 1>(src, abar, n, i, dbuf, ub / l, ub % l, DG, l, a.bg_bits);
                 if (DOUBLE) {
                     // prefetch the next block of the (i, pass, ub) sequence
                     int ni = i, nub = ub + 1, npass = pass;
@@ -338,7 +342,7 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
                 // (double-buffered: the slot read below was stored before the
                 // previous block's closing barrier)
                 const uint8_t* kslot = kbuf + (DOUBLE ? (size_t)(t & 1) * KSLOT : 0);
-                const int8_t* dblk = dbuf + (DALL ? (size_t)ub * R * 1024 : 0);
+                const int8_t* dblk = dbuf + (size_t)(DALL ? ub : ub % DG) * R * 1024;
                 mfma_block<T, R, RP>(kslot, dblk, v, jr, pass, delta);
                 if (DOUBLE) KEY_STORE(kbuf + (size_t)((t + 1) & 1) * KSLOT);
                 __syncthreads();
@@ -401,9 +405,9 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     }
 }
 
-template <typename T, int R, int RP, bool DALL>
+template <typename T, int R, int RP, int DG>
 int launch_t(tfhe_ctx* c, const BrArgs& a, size_t lds, hipStream_t s) {
-    auto k = br_mfma_kernel<T, R, RP, DALL>;
+    auto k = br_mfma_kernel<T, R, RP, DG>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return hip_check(c, e, "hipFuncSetAttribute(br_mfma)");
     const unsigned grid = (a.B + CTS - 1) / CTS;
@@ -411,26 +415,29 @@ int launch_t(tfhe_ctx* c, const BrArgs& a, size_t lds, hipStream_t s) {
     return hip_check(c, hipGetLastError(), "launch br_mfma");
 }
 
-size_t lds_need(const tfhe_ctx* c, bool dall) {
+// LDS bytes of the kernel with digit group dg (0 = all blocks of a step).
+size_t lds_need(const tfhe_ctx* c, int dg) {
     const int N = c->p.N, l = c->p.l;
     const int NL = c->q == 32 ? 4 : 8;
     const size_t kslot = 2ull * NL * 2 * N;
     size_t b = (((size_t)CTS * c->p.n * 2) + 15) & ~(size_t)15;
-    b += (size_t)(dall ? 2 * l : 1) * (N / 64) * 1024;
-    b += (dall ? 2 : 1) * kslot;
+    b += (size_t)(dg == 0 ? 2 * l : dg) * (N / 64) * 1024;
+    b += (dg == 0 ? 2 : 1) * kslot;
     return b;
 }
 
+// Largest digit group that fits LDS and the digit_blocks knob (0 auto,
+// 1 one block, 2 pairs of levels when l is even).
 template <typename T, int R, int RP>
-int dispatch_dall(tfhe_ctx* c, const BrArgs& a, hipStream_t s) {
+int dispatch_dg(tfhe_ctx* c, const BrArgs& a, hipStream_t s) {
     const size_t max_lds = (size_t)c->prop.maxSharedMemoryPerMultiProcessor > 0
                                ? (size_t)c->prop.maxSharedMemoryPerMultiProcessor
                                : (size_t)160 * 1024;
-    size_t need = lds_need(c, true);
-    if (need <= max_lds && c->digit_blocks == 0) return launch_t<T, R, RP, true>(c, a, need, s);
-    need = lds_need(c, false);
-    if (need > max_lds) return ctx_fail(c, TFHE_EINVAL, "parameters exceed LDS capacity of the MFMA kernel");
-    return launch_t<T, R, RP, false>(c, a, need, s);
+    if (c->digit_blocks == 0 && lds_need(c, 0) <= max_lds) return launch_t<T, R, RP, 0>(c, a, lds_need(c, 0), s);
+    if (c->digit_blocks != 1 && c->p.l % 2 == 0 && lds_need(c, 2) <= max_lds)
+        return launch_t<T, R, RP, 2>(c, a, lds_need(c, 2), s);
+    if (lds_need(c, 1) > max_lds) return ctx_fail(c, TFHE_EINVAL, "parameters exceed LDS capacity of the MFMA kernel");
+    return launch_t<T, R, RP, 1>(c, a, lds_need(c, 1), s);
 }
 
 }  // namespace
@@ -444,7 +451,7 @@ bool mfma_row_pass_supported(const tfhe_ctx* c, int rp) {
         if (N == 1024) return rp == 16 || rp == 8;
         return false;
     }
-    if (N == 2048) return rp == 4 || rp == 8;
+    if (N == 2048) return rp == 8 || rp == 4;
     return false;
 }
 
@@ -470,19 +477,20 @@ int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_
     const int rp = c->row_pass;
     if (c->q == 32) {
         switch (N) {
-            case 64: return dispatch_dall<uint32_t, 1, 1>(c, a, s);
-            case 256: return rp == 2 ? dispatch_dall<uint32_t, 4, 2>(c, a, s) : dispatch_dall<uint32_t, 4, 4>(c, a, s);
-            case 512: return rp == 4 ? dispatch_dall<uint32_t, 8, 4>(c, a, s) : dispatch_dall<uint32_t, 8, 8>(c, a, s);
-            case 1024: return rp == 8 ? dispatch_dall<uint32_t, 16, 8>(c, a, s) : dispatch_dall<uint32_t, 16, 16>(c, a, s);
-            case 2048: return dispatch_dall<uint32_t, 32, 8>(c, a, s);
+            case 64: return dispatch_dg<uint32_t, 1, 1>(c, a, s);
+            case 256: return rp == 2 ? dispatch_dg<uint32_t, 4, 2>(c, a, s) : dispatch_dg<uint32_t, 4, 4>(c, a, s);
+            case 512: return rp == 4 ? dispatch_dg<uint32_t, 8, 4>(c, a, s) : dispatch_dg<uint32_t, 8, 8>(c, a, s);
+            case 1024: return rp == 8 ? dispatch_dg<uint32_t, 16, 8>(c, a, s) : dispatch_dg<uint32_t, 16, 16>(c, a, s);
+            case 2048: return dispatch_dg<uint32_t, 32, 8>(c, a, s);
         }
     } else {
         switch (N) {
-            case 64: return dispatch_dall<uint64_t, 1, 1>(c, a, s);
-            case 256: return dispatch_dall<uint64_t, 4, 4>(c, a, s);
-            case 512: return dispatch_dall<uint64_t, 8, 4>(c, a, s);
-            case 1024: return dispatch_dall<uint64_t, 16, 4>(c, a, s);
-            case 2048: return rp == 8 ? dispatch_dall<uint64_t, 32, 8>(c, a, s) : dispatch_dall<uint64_t, 32, 4>(c, a, s);
+            case 64: return dispatch_dg<uint64_t, 1, 1>(c, a, s);
+            case 256: return dispatch_dg<uint64_t, 4, 4>(c, a, s);
+            case 512: return dispatch_dg<uint64_t, 8, 4>(c, a, s);
+            case 1024: return dispatch_dg<uint64_t, 16, 4>(c, a, s);
+            case 2048:
+                return rp == 4 ? dispatch_dg<uint64_t, 32, 4>(c, a, s) : dispatch_dg<uint64_t, 32, 8>(c, a, s);
         }
     }
     return ctx_fail(c, TFHE_EINVAL, "unsupported N for the MFMA kernel");

@@ -132,7 +132,7 @@ struct tfhe_ctx {
     int kernel = TFHE_KERNEL_MFMA;
     uint32_t max_batch = 65536;  // ciphertexts per blind-rotation launch in circuits
     int row_pass = 0;            // MFMA row tiles per pass (0 = default)
-    int digit_blocks = 0;        // 1: force one digit block at a time
+    int digit_blocks = 0;        // 0 auto, 1 one digit block at a time, 2 pairs of levels
     void* d_radix_tv = nullptr;  // radix look-up test polynomials [8][N] words
     void* d_bsk = nullptr;     // [n][(k+1)l][k+1][N] words
     int8_t* d_bsk8 = nullptr;  // [n][(k+1)l][k+1][LIMBS][2N] Toeplitz limb form

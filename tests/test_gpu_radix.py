@@ -58,11 +58,12 @@ def value(bl):
     return sum(int(b) << (4 * i) for i, b in enumerate(bl))
 
 
-@pytest.mark.parametrize("digit_blocks", [0, 1])
+@pytest.mark.parametrize("digit_blocks", [0, 1, 2])
 @pytest.mark.parametrize("pname", ["toy", "tiny64"])
 def test_bootstrap_per_block_digit_path(pname, digit_blocks):
-    """Digits formed one (u,p) block at a time (the path the 2048-coefficient
-    64-bit set takes) give the oracle's bits too."""
+    """Digits formed all at once, one (u,p) block at a time, or two levels of a
+    component at a time (the grouping the 2048-coefficient 64-bit set takes)
+    give the oracle's bits."""
     p = si.PARAMS[pname]
     K, ctx = keys(pname)
     ctx.set_tuning(digit_blocks=digit_blocks)
