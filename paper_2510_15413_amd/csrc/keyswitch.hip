@@ -2,92 +2,139 @@
 // out = (0^n, b') - sum_{i<kN} sum_{j<t} KSK[i][j][v_ij], where v_ij is the
 // j-th most significant base-2^b digit of a'_i rounded (ties up) to t*b bits.
 //
-// A workgroup owns a tile of 64 output words x 64 ciphertexts; thread
-// (word x, group y) accumulates 16 ciphertexts of one output word.  For each
-// (i, j) the 2^b table rows of the word are read once (coalesced across the
-// 64 words of the tile) and selected per ciphertext; the rounded inputs of
-// the tile are staged in LDS one chunk of 64 input coefficients at a time.
+// Mapping.  Lanes are ciphertexts: a workgroup of 4 waves owns 256
+// ciphertexts (64 per wave) and a tile of WPW output words, and every lane
+// accumulates those WPW words of its own ciphertext in registers.  The digit
+// that picks a table row is then a per-lane value, so the pick is an LDS
+// address rather than a select chain.  For each input coefficient i the
+// t*2^b table rows restricted to the tile's words are staged in LDS (double
+// buffered; each thread loads its share of coefficient i+1 into registers
+// while coefficient i is consumed), and each lane reads the row its digit
+// selects with 16-byte LDS reads.  Rows are padded by 16 bytes so that the
+// lanes' distinct rows fall on different bank groups.
 #include "fhesql_internal.h"
 
 namespace {
 
-constexpr int TW = 64;       // output words per tile
-constexpr int TC = 64;       // ciphertexts per tile
 constexpr int THREADS = 256;
-constexpr int PER = TC / (THREADS / TW);  // ciphertexts per thread (16)
-constexpr int ICH = 64;      // input coefficients per LDS chunk
+constexpr int TC = 256;     // ciphertexts per workgroup (one per thread)
+constexpr int PMAX = 8;     // staged elements per thread and coefficient (t*2^b*WPW <= PMAX*THREADS)
 
-template <typename T, int V>
+template <typename T>
+struct Vec16;  // 16 bytes of table words
+template <>
+struct Vec16<uint32_t> {
+    typedef uint32_t type __attribute__((ext_vector_type(4)));
+    static constexpr int N = 4;
+};
+template <>
+struct Vec16<uint64_t> {
+    typedef uint64_t type __attribute__((ext_vector_type(2)));
+    static constexpr int N = 2;
+};
+
+template <typename T, int V, int WPW>
 __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict__ big, const T* __restrict__ ksk,
-                                                            T* out, const uint64_t* out_ptrs, int B, int n,
-                                                            int kN, int t, int bb) {
-    __shared__ uint32_t rt[TC][ICH + 1];
-    const int tx = threadIdx.x % TW, ty = threadIdx.x / TW;
-    const int w = blockIdx.x * TW + tx;
-    const int c0 = blockIdx.y * TC;
-    const int tb = t * bb;
-    T acc[PER];
-#pragma unroll
-    for (int s = 0; s < PER; s++) {
-        const int c = c0 + ty + s * (THREADS / TW);
-        acc[s] = (w == n && c < B) ? big[(size_t)c * (kN + 1) + kN] : (T)0;
-    }
+                                                            T* out, const uint64_t* out_ptrs, int B, int n, int kN,
+                                                            int t, int bb) {
+    typedef typename Vec16<T>::type vec;
+    constexpr int EV = Vec16<T>::N;          // words per 16-byte read
+    constexpr int RS = WPW + EV;             // LDS row stride in words (16-byte pad)
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    T* tab = (T*)smem;                       // [2][t*V][RS]
+    const int TS = t * V * RS;               // words per buffer
+    const int tid = threadIdx.x;
+    const int c = blockIdx.y * TC + tid;
+    const int w0 = blockIdx.x * WPW;
     const size_t row = (size_t)(n + 1);
-    for (int i0 = 0; i0 < kN; i0 += ICH) {
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < TC * ICH; idx += THREADS) {
-            const int cc = idx / ICH, ii = idx % ICH;
-            const int c = c0 + cc;
-            uint32_t r = 0;
-            if (c < B && i0 + ii < kN) r = (uint32_t)round_top<T>(big[(size_t)c * (kN + 1) + i0 + ii], tb);
-            rt[cc][ii] = r;
-        }
-        __syncthreads();
-        const int iend = min(ICH, kN - i0);
-        if (w <= n) {
-            for (int ii = 0; ii < iend; ii++) {
-                const T* base = ksk + ((size_t)(i0 + ii) * t) * V * row + w;
-                for (int j = 0; j < t; j++) {
-                    T tab[V];
+    const int E = t * V * WPW;               // staged words per coefficient
+    const int tb = t * bb;
+    const bool live = c < B;
+    const T* bigc = big + (size_t)(live ? c : 0) * (kN + 1);
+
+    T acc[WPW];
 #pragma unroll
-                    for (int v = 0; v < V; v++) tab[v] = base[((size_t)j * V + v) * row];
-                    const int sh = (t - 1 - j) * bb;
+    for (int k = 0; k < WPW; k++) acc[k] = (w0 + k == n && live) ? bigc[kN] : (T)0;
+
+    // this thread's share of the tile rows of coefficient i: element e =
+    // tid + m*THREADS is word e % WPW of row (j, v) = (e / WPW / V, e / WPW % V)
+    T pf[PMAX];
+#define KS_FETCH(I)                                                                     \
+    do {                                                                                \
+        _Pragma("unroll") for (int m = 0; m < PMAX; m++) {                              \
+            const int e = tid + m * THREADS;                                            \
+            const int k = e % WPW, jv = e / WPW;                                        \
+            pf[m] = (e < E && w0 + k <= n) ? ksk[((size_t)(I) * t * V + jv) * row + w0 + k] : (T)0; \
+        }                                                                               \
+    } while (0)
+#define KS_STAGE(BUF)                                                                   \
+    do {                                                                                \
+        _Pragma("unroll") for (int m = 0; m < PMAX; m++) {                              \
+            const int e = tid + m * THREADS;                                            \
+            if (e < E) tab[(size_t)(BUF) * TS + (e / WPW) * RS + e % WPW] = pf[m];      \
+        }                                                                               \
+    } while (0)
+
+    KS_FETCH(0);
+    KS_STAGE(0);
+    __syncthreads();
+    for (int i = 0; i < kN; i++) {
+        if (i + 1 < kN) KS_FETCH(i + 1);
+        const uint32_t r = live ? (uint32_t)round_top<T>(bigc[i], tb) : 0u;
+        const T* tbuf = tab + (size_t)(i & 1) * TS;
+        for (int j = 0; j < t; j++) {
+            const uint32_t d = (r >> ((t - 1 - j) * bb)) & (V - 1);
+            const vec* rp = (const vec*)(tbuf + (j * V + d) * RS);
 #pragma unroll
-                    for (int s = 0; s < PER; s++) {
-                        const uint32_t v = (rt[ty + s * (THREADS / TW)][ii] >> sh) & (V - 1);
-                        T sel = tab[0];
+            for (int q = 0; q < WPW / EV; q++) {
+                const vec x = rp[q];
 #pragma unroll
-                        for (int q = 1; q < V; q++) sel = v == (uint32_t)q ? tab[q] : sel;
-                        acc[s] -= sel;
-                    }
-                }
+                for (int e = 0; e < EV; e++) acc[q * EV + e] -= x[e];
             }
         }
+        if (i + 1 < kN) KS_STAGE((i + 1) & 1);
+        __syncthreads();
     }
-    if (w <= n) {
+#undef KS_FETCH
+#undef KS_STAGE
+    if (!live) return;
+    T* dst = out_ptrs ? (T*)(uintptr_t)out_ptrs[c] : out + (size_t)c * row;
 #pragma unroll
-        for (int s = 0; s < PER; s++) {
-            const int c = c0 + ty + s * (THREADS / TW);
-            if (c >= B) continue;
-            T* dst = out_ptrs ? (T*)(uintptr_t)out_ptrs[c] : out + (size_t)c * row;
-            dst[w] = acc[s];
-        }
-    }
+    for (int k = 0; k < WPW; k++)
+        if (w0 + k <= n) dst[w0 + k] = acc[k];
+}
+
+template <typename T, int V, int WPW>
+int launch_v(tfhe_ctx* c, const T* big, T* out, const uint64_t* out_ptrs, uint32_t B, hipStream_t s) {
+    const int n = (int)c->p.n, kN = (int)(c->p.k * c->p.N), t = (int)c->p.ks_t, bb = (int)c->p.ks_base_bits;
+    if (t * V * WPW > PMAX * THREADS) return ctx_fail(c, TFHE_EINVAL, "key-switching levels exceed the staging tile");
+    constexpr int RS = WPW + Vec16<T>::N;
+    const size_t lds = 2ull * t * V * RS * sizeof(T);
+    auto k = keyswitch_kernel<T, V, WPW>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return hip_check(c, e, "hipFuncSetAttribute(keyswitch)");
+    dim3 grid((n + 1 + WPW - 1) / WPW, (B + TC - 1) / TC);
+    hipLaunchKernelGGL(k, grid, dim3(THREADS), lds, s, big, (const T*)c->d_ksk, out, out_ptrs, (int)B, n, kN, t, bb);
+    return hip_check(c, hipGetLastError(), "launch keyswitch");
+}
+
+// Words per lane: 16, or 8 when the LWE is short (fewer idle lanes in the
+// last word tile).
+template <typename T, int V>
+int launch_w(tfhe_ctx* c, const void* big, void* out, const uint64_t* out_ptrs, uint32_t B, hipStream_t s) {
+    if (c->p.n + 1 <= 128) return launch_v<T, V, 8>(c, (const T*)big, (T*)out, out_ptrs, B, s);
+    return launch_v<T, V, 16>(c, (const T*)big, (T*)out, out_ptrs, B, s);
 }
 
 template <typename T>
 int launch_ks_t(tfhe_ctx* c, const void* big, void* out, const uint64_t* out_ptrs, uint32_t B, hipStream_t s) {
-    const int n = (int)c->p.n, kN = (int)(c->p.k * c->p.N), t = (int)c->p.ks_t, bb = (int)c->p.ks_base_bits;
-    dim3 grid((n + 1 + TW - 1) / TW, (B + TC - 1) / TC);
-    const T* k = (const T*)c->d_ksk;
-    switch (bb) {
-        case 1: hipLaunchKernelGGL((keyswitch_kernel<T, 2>), grid, dim3(THREADS), 0, s, (const T*)big, k, (T*)out, out_ptrs, (int)B, n, kN, t, bb); break;
-        case 2: hipLaunchKernelGGL((keyswitch_kernel<T, 4>), grid, dim3(THREADS), 0, s, (const T*)big, k, (T*)out, out_ptrs, (int)B, n, kN, t, bb); break;
-        case 3: hipLaunchKernelGGL((keyswitch_kernel<T, 8>), grid, dim3(THREADS), 0, s, (const T*)big, k, (T*)out, out_ptrs, (int)B, n, kN, t, bb); break;
-        case 4: hipLaunchKernelGGL((keyswitch_kernel<T, 16>), grid, dim3(THREADS), 0, s, (const T*)big, k, (T*)out, out_ptrs, (int)B, n, kN, t, bb); break;
+    switch (c->p.ks_base_bits) {
+        case 1: return launch_w<T, 2>(c, big, out, out_ptrs, B, s);
+        case 2: return launch_w<T, 4>(c, big, out, out_ptrs, B, s);
+        case 3: return launch_w<T, 8>(c, big, out, out_ptrs, B, s);
+        case 4: return launch_w<T, 16>(c, big, out, out_ptrs, B, s);
         default: return ctx_fail(c, TFHE_EINVAL, "key-switching base must be 2^1..2^4");
     }
-    return hip_check(c, hipGetLastError(), "launch keyswitch");
 }
 
 }  // namespace

@@ -83,9 +83,10 @@ def _enc_table(K, rows, w, seed):
     return col1, col2, c1, c2
 
 
-def test_std_scan_4096_rows(std):
-    """The benchmark's step at full size: every row decrypts to the plaintext
-    truth and sampled rows are bit-exact to the oracle end to end."""
+@pytest.fixture(scope="module")
+def scan4096(std):
+    """The benchmark's step at full size, run once on the GPU: mask(col1 == c)
+    + select(col2) and mask(col1 < c) over 4096 rows of 8-bit columns."""
     K, ctx = std
     rows, w = 4096, 8
     col1, col2, c1, c2 = _enc_table(K, rows, w, 2)
@@ -100,23 +101,52 @@ def test_std_scan_4096_rows(std):
     ctx.sql_masked_select(m_eq, d2, rows, w, s_eq)
     ctx.sql_mask_scan(d1, rows, w, "lt", to_dev(P, lit_lt), m_lt)
     torch.cuda.synchronize()
-    gm_eq, gm_lt, gs = from_dev(P, m_eq), from_dev(P, m_lt), from_dev(P, s_eq)
+    return dict(rows=rows, w=w, col1=col1, col2=col2, c1=c1, c2=c2, c_eq=c_eq, c_lt=c_lt, lit_eq=lit_eq,
+                lit_lt=lit_lt, m_eq=from_dev(P, m_eq), m_lt=from_dev(P, m_lt), s_eq=from_dev(P, s_eq))
+
+
+def _oracle_rows(K, sc, sample, with_lt):
+    """Level-parallel oracle evaluation of the step's circuits on rows."""
+    lz = C.LazyBackend(P)
+    roots = []
+    for r in sample:
+        m = C.eq(lz, list(sc["c1"][r]), list(sc["lit_eq"]))
+        lt = C.lt(lz, list(sc["c1"][r]), list(sc["lit_lt"])) if with_lt else None
+        roots.append((r, m, C.select(lz, m, list(sc["c2"][r])), lt))
+    C.evaluate(P, K, lz, threads=oracle.default_threads())
+    return roots
+
+
+def test_std_scan_4096_rows(std, scan4096):
+    """Every row decrypts to the plaintext truth; two rows (one matching)
+    and one < chain are bit-exact to the oracle end to end."""
+    K, ctx = std
+    sc = scan4096
+    rows, w, col1, col2, c_eq, c_lt = sc["rows"], sc["w"], sc["col1"], sc["col2"], sc["c_eq"], sc["c_lt"]
+    gm_eq, gm_lt, gs = sc["m_eq"], sc["m_lt"], sc["s_eq"]
     dec = lambda cts: np.array([oracle.decrypt_bit(P.q, K.s, c) for c in cts.reshape(-1, P.n + 1)])  # noqa: E731
     assert (dec(gm_eq) == (col1 == c_eq)).all()
     assert (dec(gm_lt) == (col1 < c_lt)).all()
     vals = dec(gs).reshape(rows, w)
     assert [bits_to_int(v) for v in vals] == [int(b) if a == c_eq else 0 for a, b in zip(col1, col2)]
-    # oracle end to end on sampled rows (one matching, one not), level-parallel
-    sample = [1234, 4095]
-    lz = C.LazyBackend(P)
-    roots = []
-    for r in sample:
-        m = C.eq(lz, list(c1[r]), list(lit_eq))
-        roots.append((r, m, C.select(lz, m, list(c2[r]))))
-    mlt = C.lt(lz, list(c1[7]), list(lit_lt))
-    say("oracle end to end on rows", sample, "+ one < chain")
-    C.evaluate(P, K, lz, threads=oracle.default_threads())
-    for r, m, sel in roots:
+    say("oracle end to end on rows 1234, 4095 (+ < chain on 4095)")
+    for r, m, sel, lt in _oracle_rows(K, sc, [1234, 4095], True):
         assert np.array_equal(gm_eq[r], C.resolve(P, m)), r
         assert np.array_equal(gs[r], C.resolve(P, sel)), r
-    assert np.array_equal(gm_lt[7], C.resolve(P, mlt))
+        assert np.array_equal(gm_lt[r], C.resolve(P, lt)), r
+
+
+@pytest.mark.slow
+def test_std_scan_64_row_sample(std, scan4096):
+    """64 seeded rows of the 4096-row step bit-exact end to end: the equality
+    mask, the masked select and the < mask of each (1,984 oracle
+    bootstraps, level-parallel on the host cores)."""
+    K, _ = std
+    sc = scan4096
+    sample = sorted(set(int(x) % sc["rows"] for x in si.uniform_ints(si.DATA_SEED_BASE + 64, si.TAG_SHAPE, 63, 16)))
+    sample = sorted(set(sample) | {1234})[:64]
+    say("oracle end to end on", len(sample), "seeded rows")
+    for r, m, sel, lt in _oracle_rows(K, sc, sample, True):
+        assert np.array_equal(sc["m_eq"][r], C.resolve(P, m)), r
+        assert np.array_equal(sc["s_eq"][r], C.resolve(P, sel)), r
+        assert np.array_equal(sc["m_lt"][r], C.resolve(P, lt)), r
