@@ -103,11 +103,15 @@ int tfhe_set_kernel(tfhe_ctx* ctx, int kind);
  * Returns TFHE_EINVAL for an unknown key or unsupported value. */
 #define TFHE_TUNE_MAX_BATCH 1
 #define TFHE_TUNE_ROW_PASS 2
-/*   TFHE_TUNE_DIGIT_BLOCKS 0 = the largest digit grouping that fits in LDS
- *                        (default): all blocks of a CMux step at once, else
+/*   TFHE_TUNE_DIGIT_BLOCKS 0 = the best digit grouping that fits in LDS
+ *                        (default): with one MFMA row pass, one component's
+ *                        blocks at a time with accumulator component 0 held
+ *                        in LDS; else all blocks of a CMux step at once, else
  *                        pairs of levels of one component (l even), else one
  *                        (u,p) block at a time; 1 = one block at a time;
- *                        2 = pairs when l is even and they fit, else one. */
+ *                        2 = pairs when l is even and they fit, else one;
+ *                        3 = all blocks of a step, accumulator in global
+ *                        memory, when they fit. */
 #define TFHE_TUNE_DIGIT_BLOCKS 3
 int tfhe_set_tuning(tfhe_ctx* ctx, int key, int64_t value);
 

@@ -57,8 +57,8 @@ FHE_DEV size_t acc_idx(int N, int v, int j, int c) {
 // words straddle at most two such groups, so an item takes three vector
 // loads; the loads of G items are issued together.
 template <typename T, int R, int U>
-FHE_DEV void digits_phase(const T* __restrict__ src, const uint16_t* abar, int n, int i,
-                          int8_t* dbuf, int u_lo, int p_lo, int p_n, int l, int bgb) {
+FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u_lo, int p_lo, int p_n, int l,
+                          int bgb) {
     typedef T vec4 __attribute__((ext_vector_type(4)));
     constexpr int N = R * 64;
     constexpr int NG = N / 4;  // 4-word groups per component
@@ -70,8 +70,7 @@ FHE_DEV void digits_phase(const T* __restrict__ src, const uint16_t* abar, int n
     const int half = 1 << (bgb - 1);
     uint32_t off = 0;
     for (int p = 0; p < l; p++) off += (uint32_t)half << (p * bgb);
-    const int c = threadIdx.x & (CTS - 1);  // fixed per thread (THREADS % 16 == 0)
-    const int ab = abar[c * n + i];
+    const int c = threadIdx.x & (CTS - 1);  // fixed per thread (THREADS % 16 == 0); ab is its abar_i
     const int neg = ab >= N;
     const int es = neg ? ab - N : ab;
     // coefficient 4kg+e reads rotated index 4kg+e-es: group kg-qs (+1), lane sh
@@ -219,8 +218,10 @@ FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr,
 }
 
 // DG: digit blocks formed per rotate-diff pass -- 0 all (k+1)l blocks of a
-// step up front (key double-buffered), else DG consecutive levels of one
-// component just before their MFMA blocks.
+// step up front (key double-buffered), -1 the l blocks of one component
+// before that component's MFMA blocks with accumulator component 0 held in
+// LDS (key double-buffered), else DG consecutive levels of one component just
+// before their MFMA blocks.
 template <typename T, int R, int RP, int DG>
 __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void br_mfma_kernel(BrArgs a) {
     constexpr int N = R * 64;
@@ -228,31 +229,36 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     constexpr int KSLOT = 2 * NL * 2 * N;  // bytes of one (u,p) key block
     constexpr int KV = (KSLOT / 16 + THREADS - 1) / THREADS;
     constexpr int LG = __builtin_ctz(2 * N);
-    constexpr bool DALL = DG == 0;
+    constexpr bool ACCL = DG < 0;
+    constexpr bool DALL = DG <= 0;   // a step's digits formed before its blocks run
     constexpr bool DOUBLE = DALL;
+    constexpr int NPASS = R / RP;
+    static_assert(!ACCL || NPASS == 1, "LDS accumulator mode needs one row pass");
     const int n = a.n, l = a.l, NB = 2 * l;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int ct0 = blockIdx.x * CTS;
     const T* lwe = (const T*)a.lwe;
 
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    uint16_t* abar = (uint16_t*)smem;
-    size_t off = ((size_t)CTS * n * 2 + 15) & ~(size_t)15;
-    int8_t* dbuf = (int8_t*)(smem + off);
-    off += (size_t)(DALL ? NB : DG) * R * 1024;
+    int8_t* dbuf = (int8_t*)smem;
+    size_t off = (size_t)(ACCL ? l : DALL ? NB : DG) * R * 1024;
     uint8_t* kbuf = smem + off;
+    off += (size_t)(DOUBLE ? 2 : 1) * KSLOT;
+    T* acc0 = (T*)(smem + off);  // ACCL: accumulator component 0, [N/4][16 cts][4]
 
-    // With all digits of a step formed up front (DALL) the accumulator is
-    // updated in place; otherwise two buffers alternate per step.
+    // With all digits of a step formed before its blocks (DALL) the
+    // accumulator is updated in place; otherwise two buffers alternate.
     T* ws0 = (T*)a.ws + (size_t)blockIdx.x * (DALL ? 1 : 2) * (2 * N * CTS);
     T* ws1 = DALL ? ws0 : ws0 + 2 * N * CTS;
+    T* const acc1 = ws0 + (size_t)N * CTS;  // ACCL: component 1 in global memory
 
-    // ---- prologue: modulus switch, accumulator = (0, X^{-bbar} testv)
-    for (int idx = tid; idx < CTS * n; idx += THREADS) {
-        const int c = idx / n, i = idx - c * n;
-        const int gi = ct0 + c;
-        abar[idx] = gi < a.B ? (uint16_t)mod_switch<T>(lwe[(size_t)gi * (n + 1) + i], LG) : 0;
-    }
+    // this thread's ciphertext in the digit phases and its abar_i, one step ahead
+    const int cd = tid & (CTS - 1);
+    const T* lwe_cd = lwe + (size_t)(ct0 + cd < a.B ? ct0 + cd : 0) * (n + 1);
+    const bool cd_live = ct0 + cd < a.B;
+    T a_next = cd_live ? lwe_cd[0] : (T)0;  // raw a_{i+1}; switched when used
+
+    // ---- prologue: accumulator = (0, X^{-bbar} testv)
     for (int idx = tid; idx < CTS * N; idx += THREADS) {
         const int c = idx & (CTS - 1), j = idx >> 4;
         const int gi = ct0 + c;
@@ -263,12 +269,12 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
             const T* tv = (const T*)a.tv + (size_t)(a.tv_index ? a.tv_index[gi] : 0) * N;
             body = monomial_coef<T>([&](int s) -> T { return tv[s]; }, N, e, j);
         }
-        ws0[acc_idx<T>(N, 0, j, c)] = 0;
+        if (ACCL) acc0[acc_idx<T>(N, 0, j, c)] = 0;
+        else ws0[acc_idx<T>(N, 0, j, c)] = 0;
         ws0[acc_idx<T>(N, 1, j, c)] = body;
     }
 
     const int v = wave >> 2, jr = wave & 3;
-    constexpr int NPASS = R / RP;
     constexpr int KU = KSLOT / 16;  // uint4 per key block
     uint4 pre[KV];
 #define KEY_LOAD(SRCPTR)                                                   \
@@ -299,23 +305,26 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     int t = 0;  // linear key-block counter over (i, pass, ub)
     // With one pass and in-place accumulators each wave keeps its own rows
     // in registers across steps (the fold accumulates straight into them) and
-    // only stores them for the next step's digit phase.
+    // only stores them for the next step's digit phases.
     constexpr bool REGACC = DALL && NPASS == 1;
     typedef T vec4 __attribute__((ext_vector_type(4)));
     constexpr size_t STEP4 = (size_t)(64 / 4) * CTS * 4;  // 4 row tiles further
     const size_t rbase = acc_idx<T>(N, v, 16 * jr + 4 * (lane >> 4), lane & 15);
+    T* const rowp = (ACCL && v == 0) ? acc0 + rbase : ws0 + rbase;  // this wave's rows
     T accr[REGACC ? RP : 1][4];
     if (REGACC) {
 #pragma unroll
         for (int q = 0; q < (REGACC ? RP : 1); q++) {
-            const vec4 x = *(const vec4*)(ws0 + rbase + q * STEP4);
+            const vec4 x = *(const vec4*)(rowp + q * STEP4);
 #pragma unroll
             for (int e = 0; e < 4; e++) accr[q][e] = x[e];
         }
     }
     for (int i = 0; i < n; i++) {
-        if (DALL) {
-            digits_phase<T, R, 2>(src, abar, n, i, dbuf, 0, 0, l, l, a.bg_bits);
+        const int ab = cd_live ? (int)mod_switch<T>(a_next, LG) : 0;
+        if (i + 1 < n) a_next = lwe_cd[i + 1];
+        if (DALL && !ACCL) {
+            digits_phase<T, R, 2>(src, ab, dbuf, 0, 0, l, l, a.bg_bits);
             __syncthreads();
         }
         for (int pass = 0; pass < NPASS; pass++) {
@@ -328,7 +337,14 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
                     for (int e = 0; e < 4; e++) delta[q][e] = 0;
             }
             for (int ub = 0; ub < NB; ub++, t++) {
-                if (!DALL && ub % DG == 0) digits_phase<T, R, 1>(src, abar, n, i, dbuf, ub / l, ub % l, DG, l, a.bg_bits);
+                if (ACCL && ub % l == 0) {
+                    // digits of component ub/l (its MFMA blocks of the last
+                    // component ended with a barrier)
+                    if (ub == 0) digits_phase<T, R, 1>(acc0, ab, dbuf, 0, 0, l, l, a.bg_bits);
+                    else digits_phase<T, R, 1>(acc1, ab, dbuf, 0, 0, l, l, a.bg_bits);
+                    __syncthreads();
+                }
+                if (!DALL && ub % DG == 0) digits_phase<T, R, 1>(src, ab, dbuf, ub / l, ub % l, DG, l, a.bg_bits);
                 if (DOUBLE) {
                     // prefetch the next block of the (i, pass, ub) sequence
                     int ni = i, nub = ub + 1, npass = pass;
@@ -342,13 +358,13 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
                 // (double-buffered: the slot read below was stored before the
                 // previous block's closing barrier)
                 const uint8_t* kslot = kbuf + (DOUBLE ? (size_t)(t & 1) * KSLOT : 0);
-                const int8_t* dblk = dbuf + (size_t)(DALL ? ub : ub % DG) * R * 1024;
+                const int8_t* dblk = dbuf + (size_t)(ACCL ? ub % l : DALL ? ub : ub % DG) * R * 1024;
                 mfma_block<T, R, RP>(kslot, dblk, v, jr, pass, delta);
                 if (DOUBLE) KEY_STORE(kbuf + (size_t)((t + 1) & 1) * KSLOT);
                 __syncthreads();
             }
             if (REGACC) {
-                T* pd = dst + rbase;
+                T* pd = ACCL ? rowp : dst + rbase;
                 __asm__ volatile("" : "+v"(pd));
 #pragma unroll
                 for (int q = 0; q < RP; q++) {
@@ -363,7 +379,6 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
             // loads issued before the stores).  Row tile J = jr + 4a holds
             // coefficients 16J + 4(lane>>4) + e of ciphertext lane&15.
             {
-                typedef T vec4 __attribute__((ext_vector_type(4)));
                 const size_t base0 = acc_idx<T>(N, v, 16 * (jr + 4 * pass * RP) + 4 * (lane >> 4), lane & 15);
                 constexpr size_t STEP = (size_t)(64 / 4) * CTS * 4;  // 4 row tiles further
                 // opaque per step, so the 2*RP row addresses are formed here
@@ -392,14 +407,15 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
 #undef KEY_LOAD
 #undef KEY_STORE
     // ---- sample extraction: a'_0 = A[0], a'_j = -A[N-j], b' = B[0]
+    const T* A0 = ACCL ? (const T*)acc0 : src;
     T* out = (T*)a.out;
     for (int idx = tid; idx < CTS * (N + 1); idx += THREADS) {
         const int c = idx / (N + 1), j = idx - c * (N + 1);
         const int gi = ct0 + c;
         if (gi >= a.B) continue;
         T val;
-        if (j == 0) val = src[acc_idx<T>(N, 0, 0, c)];
-        else if (j < N) val = (T)(0 - src[acc_idx<T>(N, 0, N - j, c)]);
+        if (j == 0) val = A0[acc_idx<T>(N, 0, 0, c)];
+        else if (j < N) val = (T)(0 - A0[acc_idx<T>(N, 0, N - j, c)]);
         else val = src[acc_idx<T>(N, 1, 0, c)];
         out[(size_t)gi * (N + 1) + j] = val;
     }
@@ -415,25 +431,32 @@ int launch_t(tfhe_ctx* c, const BrArgs& a, size_t lds, hipStream_t s) {
     return hip_check(c, hipGetLastError(), "launch br_mfma");
 }
 
-// LDS bytes of the kernel with digit group dg (0 = all blocks of a step).
+// LDS bytes of the kernel with digit group dg (0 = all blocks of a step,
+// -1 = one component's blocks plus accumulator component 0).
 size_t lds_need(const tfhe_ctx* c, int dg) {
     const int N = c->p.N, l = c->p.l;
     const int NL = c->q == 32 ? 4 : 8;
     const size_t kslot = 2ull * NL * 2 * N;
-    size_t b = (((size_t)CTS * c->p.n * 2) + 15) & ~(size_t)15;
-    b += (size_t)(dg == 0 ? 2 * l : dg) * (N / 64) * 1024;
-    b += (dg == 0 ? 2 : 1) * kslot;
+    size_t b = (size_t)(dg < 0 ? l : dg == 0 ? 2 * l : dg) * (N / 64) * 1024;
+    b += (dg <= 0 ? 2 : 1) * kslot;
+    if (dg < 0) b += (size_t)N * CTS * word_bytes(c);
     return b;
 }
 
-// Largest digit group that fits LDS and the digit_blocks knob (0 auto,
-// 1 one block, 2 pairs of levels when l is even).
+// Largest digit grouping that fits LDS and the digit_blocks knob (0 auto,
+// 1 one block, 2 pairs of levels when l is even, 3 all blocks of a step with
+// the accumulator in global memory).  Auto prefers, with one row pass, the
+// per-component grouping that keeps accumulator component 0 in LDS.
 template <typename T, int R, int RP>
 int dispatch_dg(tfhe_ctx* c, const BrArgs& a, hipStream_t s) {
     const size_t max_lds = (size_t)c->prop.maxSharedMemoryPerMultiProcessor > 0
                                ? (size_t)c->prop.maxSharedMemoryPerMultiProcessor
                                : (size_t)160 * 1024;
-    if (c->digit_blocks == 0 && lds_need(c, 0) <= max_lds) return launch_t<T, R, RP, 0>(c, a, lds_need(c, 0), s);
+    if constexpr (RP == R) {
+        if (c->digit_blocks == 0 && lds_need(c, -1) <= max_lds) return launch_t<T, R, RP, -1>(c, a, lds_need(c, -1), s);
+    }
+    if ((c->digit_blocks == 0 || c->digit_blocks == 3) && lds_need(c, 0) <= max_lds)
+        return launch_t<T, R, RP, 0>(c, a, lds_need(c, 0), s);
     if (c->digit_blocks != 1 && c->p.l % 2 == 0 && lds_need(c, 2) <= max_lds)
         return launch_t<T, R, RP, 2>(c, a, lds_need(c, 2), s);
     if (lds_need(c, 1) > max_lds) return ctx_fail(c, TFHE_EINVAL, "parameters exceed LDS capacity of the MFMA kernel");

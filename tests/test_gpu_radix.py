@@ -58,12 +58,14 @@ def value(bl):
     return sum(int(b) << (4 * i) for i, b in enumerate(bl))
 
 
-@pytest.mark.parametrize("digit_blocks", [0, 1, 2])
+@pytest.mark.parametrize("digit_blocks", [0, 1, 2, 3])
 @pytest.mark.parametrize("pname", ["toy", "tiny64"])
 def test_bootstrap_per_block_digit_path(pname, digit_blocks):
-    """Digits formed all at once, one (u,p) block at a time, or two levels of a
-    component at a time (the grouping the 2048-coefficient 64-bit set takes)
-    give the oracle's bits."""
+    """Every digit grouping gives the oracle's bits: one component's blocks with
+    accumulator component 0 in LDS (the default with one row pass), one (u,p)
+    block at a time, two levels of a component at a time (the 2048-coefficient
+    64-bit set's grouping), and all blocks of a step with the accumulator in
+    global memory."""
     p = si.PARAMS[pname]
     K, ctx = keys(pname)
     ctx.set_tuning(digit_blocks=digit_blocks)
