@@ -59,6 +59,26 @@ def cpu_baseline(p, threads, per_thread):
                       f"{dt:.1f} s wall"}
 
 
+def keyswitch_counters():
+    """HBM rate of the 4096-ciphertext key switch from the committed counter
+    summary, or None when keyswitch.hip has changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "keyswitch_std_batch4096_counters.json")
+    src = os.path.join(ROOT, "paper_2510_15413_amd", "csrc", "keyswitch.hip")
+    try:
+        with open(path) as f:
+            prof = json.load(f)
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if prof.get("source_sha256_16") != h:
+        return None
+    return {"kernel": "keyswitch_kernel", "hbm_gb_per_s": round(prof["hbm_gbps"], 1), "hbm_peak_gb_per_s": 8000,
+            "hbm_frac": round(prof["hbm_gbps"] / 8000, 4), "algorithmic_gb_per_s": round(prof["algorithmic_gbps"], 1),
+            "ms_per_4096": round(prof["kernel_ms"], 3), "bound": "lds/valu (table rows staged in LDS)"}
+
+
 def counter_traffic():
     """HBM bytes per 4096-ciphertext blind-rotation launch from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by what they
@@ -534,6 +554,9 @@ def main():
         res["roofline"]["algorithmic_bytes_per_launch"] = 4096 * (p.n + 1 + p.N + 1) * 4 + \
             p.n * 2 * p.l * 2 * 4 * 2 * p.N
         res["roofline"]["mfma_busy_frac_counter"] = round(prof["mfma_busy_frac"], 4)
+    ksc = keyswitch_counters()
+    if ksc is not None:
+        res["key_switch_counters"] = ksc
 
     if not args.no_plain:
         B = 4096

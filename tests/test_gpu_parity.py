@@ -250,11 +250,21 @@ def test_scan_batch_isolation_and_parity(use_graph):
         ctx.sql_mask_scan(d["col"], rows, w, op, d["lit_a"], m1, lit_b=d["lit_b"])
         ctx.sql_masked_select(m1, d["sel_col"], rows, w, s1)
         alone.append((m1, s1))
-    ctx.sql_scan_batch(qs, use_graph=use_graph)
-    torch.cuda.synchronize()
-    for t, (d, (m1, s1)) in enumerate(zip(qs, alone)):
-        assert torch.equal(d["mask"], m1), t
-        assert torch.equal(d["sel_out"], s1), t
+    # three runs in a row with eager work and synchronizations between them;
+    # every run (each a fresh capture and replay on the graph path) must
+    # reproduce the tables computed alone
+    for rep in range(3):
+        for d in qs:
+            d["mask"].fill_(0x5A5A5A5A)
+            d["sel_out"].fill_(-1)
+        scratch = torch.arange(4096, device="cuda", dtype=torch.int64).sum()
+        torch.cuda.synchronize()
+        ctx.sql_scan_batch(qs, use_graph=use_graph)
+        torch.cuda.synchronize()
+        del scratch
+        for t, (d, (m1, s1)) in enumerate(zip(qs, alone)):
+            assert torch.equal(d["mask"], m1), (rep, t)
+            assert torch.equal(d["sel_out"], s1), (rep, t)
     # oracle end to end on the first two rows of every table
     for t, (d, (col1, col2, c1, c2, la, lb)) in enumerate(zip(qs, tabs)):
         op = specs[t][1]
