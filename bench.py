@@ -59,20 +59,30 @@ def cpu_baseline(p, threads, per_thread):
                       f"{dt:.1f} s wall"}
 
 
+def code_hash(path):
+    """sha256[:16] of a kernel source with comments and blank lines removed,
+    so that the committed counter summaries stay tied to the code alone."""
+    import hashlib
+    import re
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = [re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines()]
+    return hashlib.sha256("\n".join(ln for ln in lines if ln.strip()).encode()).hexdigest()[:16]
+
+
 def keyswitch_counters():
     """HBM rate of the 4096-ciphertext key switch from the committed counter
     summary, or None when keyswitch.hip has changed since it was taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "keyswitch_std_batch4096_counters.json")
     src = os.path.join(ROOT, "paper_2510_15413_amd", "csrc", "keyswitch.hip")
     try:
         with open(path) as f:
             prof = json.load(f)
-        with open(src, "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()[:16]
+        h = code_hash(src)
     except OSError:
         return None
-    if prof.get("source_sha256_16") != h:
+    if prof.get("code_sha256_16") != h:
         return None
     return {"kernel": "keyswitch_kernel", "hbm_gb_per_s": round(prof["hbm_gbps"], 1), "hbm_peak_gb_per_s": 8000,
             "hbm_frac": round(prof["hbm_gbps"] / 8000, 4), "algorithmic_gb_per_s": round(prof["algorithmic_gbps"], 1),
@@ -84,17 +94,15 @@ def counter_traffic():
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by what they
     read for a 256 MiB copy), or None when the kernel source has changed since
     the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "br_mfma_std_batch4096_counters.json")
     src = os.path.join(ROOT, "paper_2510_15413_amd", "csrc", "br_mfma.hip")
     try:
         with open(path) as f:
             prof = json.load(f)
-        with open(src, "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()[:16]
+        h = code_hash(src)
     except OSError:
         return None
-    if prof.get("source_sha256_16") != h:
+    if prof.get("code_sha256_16") != h:
         return None
     return prof
 

@@ -22,8 +22,12 @@
 // The key limbs of step i are stored (once per context) as reversed extended
 // byte arrays S[x] = limb(Kext[N-1-x]); a lane's 16 A bytes are contiguous
 // in S (unaligned by a per-lane constant, fixed with v_alignbyte).
-// Accumulators live in a per-workgroup global ping-pong buffer laid out
-// [v][N/4][16 cts][4 coefs] (L2/MALL resident); digits and key limbs in LDS.
+// Accumulators are laid out [v][N/4][16 cts][4 coefs].  With one row pass
+// every wave keeps its rows in registers across the n steps and stores them
+// at each step's end for the next rotate-diff: component 0 to LDS, component
+// 1 to a per-workgroup global buffer (L2 resident).  With several passes
+// both components live in a global ping-pong buffer.  Digits and key limbs
+// are staged in LDS.
 #include "fhesql_internal.h"
 
 namespace {
