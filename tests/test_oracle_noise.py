@@ -53,3 +53,24 @@ def test_noise_variances_toy(toy_keys):
     assert abs(e_br.var() / var_br - 1) < 0.2, (e_br.var(), var_br)
     assert abs(e_ks.var() / var_ks - 1) < 0.2, (e_ks.var(), var_ks)
     assert abs(e_br.mean()) < 4 * np.sqrt(var_br / samples)
+
+
+def test_forced_phase_flip_is_predicted(toy_keys):
+    """Host-forced failure: moving the body of an encryption of TRUE by
+    -(1/8 + d) puts its phase at about -d.  For d = +2^-5 the decryption and
+    the bootstrapped copy both flip to FALSE; for d = -2^-5 both stay TRUE
+    (2^-5 is about ten standard deviations of the modulus-switch rounding at
+    N = 256, and the fresh noise is 2^-20)."""
+    p = si.TOY
+    K = toy_keys
+    cts = enc_bits(p, K, [1, 1, 1, 1], 950)
+    eighth = 1 << (p.q - 3)
+    tv = oracle.gate_testv(p)
+    for d_sign, want in ((+1, 0), (-1, 1)):
+        for ct in cts:
+            c = ct.copy()
+            shift = eighth + d_sign * (1 << (p.q - 5))
+            c[p.n] = (int(c[p.n]) - shift) % (1 << p.q)
+            assert oracle.decrypt_bit(p.q, K.s, c) == want
+            out = oracle.keyswitch(p, K.ksk, oracle.bootstrap(p, K.bsk, c, tv))
+            assert oracle.decrypt_bit(p.q, K.s, out) == want
