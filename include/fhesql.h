@@ -237,6 +237,15 @@ int tfhe_timing_enable(tfhe_ctx* ctx, int on);
 int tfhe_timing_read(tfhe_ctx* ctx, int kind, uint64_t* launches, double* total_ms,
                      uint64_t* cts);
 
+/* Ordered launch log since timing was enabled (not during graph capture):
+ * for launch i, kinds[i] (0 blind rotation, 1 key switching) and sizes[i]
+ * (ciphertexts).  Copies min(max, count) entries (either array may be NULL);
+ * *count receives the number recorded (at most 2^22).  The schedule is a
+ * function of the query's structure and row counts only -- what the ideal
+ * functionality of Section 5 leaks (the AST with literals redacted and the
+ * table size) -- never of the encrypted data or literals. */
+int tfhe_timing_log(tfhe_ctx* ctx, uint32_t* kinds, uint32_t* sizes, uint64_t max, uint64_t* count);
+
 /* ---- radix integers (programmable bootstrapping with look-up tables) ----
  * An integer is nb blocks of 4-bit messages, least significant block first; a
  * block value x in [0, 32) (4 message bits + 1 carry bit) is the LWE

@@ -364,8 +364,9 @@ def _value(p, x):
     return np.asarray(x, dtype=np.uint64)
 
 
-def evaluate(p, keys, lazy: LazyBackend, threads=None):
-    """Bootstrap every recorded gate, depth by depth, on a thread pool."""
+def evaluate(p, keys, lazy: LazyBackend, threads=None, progress=None):
+    """Bootstrap every recorded gate, depth by depth, on a thread pool;
+    progress(depth_done, depths, gates_done, gates) is called after each depth."""
     by_depth = {}
     for nd in lazy.nodes:
         by_depth.setdefault(nd.depth, []).append(nd)
@@ -374,8 +375,13 @@ def evaluate(p, keys, lazy: LazyBackend, threads=None):
     def run(nd):
         nd.val = cb.gate(nd.op, *[_value(p, x) for x in nd.ins])
 
-    for d in sorted(by_depth):
+    depths = sorted(by_depth)
+    total, done = len(lazy.nodes), 0
+    for i, d in enumerate(depths):
         parallel_map(run, by_depth[d], threads)
+        done += len(by_depth[d])
+        if progress:
+            progress(i + 1, len(depths), done, total)
 
 
 def resolve(p, x):

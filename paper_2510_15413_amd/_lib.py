@@ -34,7 +34,7 @@ EXPORTS = [
     "tfhe_lwe_encrypt", "tfhe_lwe_phase", "tfhe_timing_enable", "tfhe_timing_read",
     "tfhe_set_tuning", "sql_server_create", "sql_server_destroy", "sql_server_submit",
     "sql_server_step", "sql_server_done", "sql_server_bytes_in_use",
-    "sql_radix_mask_scan", "sql_radix_masked_select", "sql_radix_sum", "sql_expr_eval",
+    "sql_radix_mask_scan", "sql_radix_masked_select", "sql_radix_sum", "sql_expr_eval", "tfhe_timing_log",
 ]
 # Expression-tree node kinds and comparison operators (sql_expr).
 SQL_EXPR_KINDS = {"column": 0, "const": 1, "literal": 2, "cmp": 3, "and": 4, "or": 5, "xor": 6, "not": 7,
@@ -116,6 +116,7 @@ def load():
         "sql_radix_mask_scan": (i32, [vp, vp, u32, u32, i32, vp, vp, vp]),
         "sql_radix_masked_select": (i32, [vp, vp, vp, u32, u32, vp, vp]),
         "sql_radix_sum": (i32, [vp, vp, u32, u32, vp, vp]),
+        "tfhe_timing_log": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), u64, ctypes.POINTER(u64)]),
         "sql_expr_eval": (i32, [vp, ctypes.POINTER(vp), u32, u32, u32, ctypes.POINTER(SqlExpr), u32, vp, vp]),
         "tfhe_timing_read": (i32, [vp, i32, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(u64)]),
@@ -212,6 +213,18 @@ class Context:
         self._rc(load().tfhe_timing_read(self._h, 0 if kind == "br" else 1, ctypes.byref(n), ctypes.byref(ms),
                                          ctypes.byref(cts)), "tfhe_timing_read")
         return n.value, ms.value, cts.value
+
+    def timing_log(self):
+        """[(kind, ciphertexts)] of every launch since timing was enabled, in
+        order; kind is 'br' or 'ks'."""
+        L = load()
+        cnt = ctypes.c_uint64()
+        self._rc(L.tfhe_timing_log(self._h, None, None, 0, ctypes.byref(cnt)), "tfhe_timing_log")
+        n = cnt.value
+        k = (ctypes.c_uint32 * max(1, n))()
+        z = (ctypes.c_uint32 * max(1, n))()
+        self._rc(L.tfhe_timing_log(self._h, k, z, n, ctypes.byref(cnt)), "tfhe_timing_log")
+        return [("br" if k[i] == 0 else "ks", int(z[i])) for i in range(n)]
 
     def set_tuning(self, max_batch=None, row_pass=None, digit_blocks=None):
         L = load()

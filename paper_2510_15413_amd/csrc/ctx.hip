@@ -258,6 +258,7 @@ static int timing_drain(tfhe_ctx* c) {
         c->t_launch[t.kind]++;
         c->t_ms[t.kind] += ms;
         c->t_cts[t.kind] += t.cts;
+        if (c->t_log.size() < (1u << 22)) c->t_log.push_back(((uint64_t)t.kind << 32) | t.cts);
         c->event_pool.push_back(t.a);
         c->event_pool.push_back(t.b);
     }
@@ -271,6 +272,20 @@ extern "C" int tfhe_timing_enable(tfhe_ctx* c, int on) {
     if (rc) return rc;
     c->timing = on != 0;
     for (int k = 0; k < 2; k++) { c->t_launch[k] = 0; c->t_ms[k] = 0; c->t_cts[k] = 0; }
+    c->t_log.clear();
+    return TFHE_OK;
+}
+
+extern "C" int tfhe_timing_log(tfhe_ctx* c, uint32_t* kinds, uint32_t* sizes, uint64_t max, uint64_t* count) {
+    if (!c) return TFHE_EINVAL;
+    int rc = timing_drain(c);
+    if (rc) return rc;
+    const uint64_t n = c->t_log.size();
+    if (count) *count = n;
+    for (uint64_t i = 0; i < n && i < max; i++) {
+        if (kinds) kinds[i] = (uint32_t)(c->t_log[i] >> 32);
+        if (sizes) sizes[i] = (uint32_t)c->t_log[i];
+    }
     return TFHE_OK;
 }
 

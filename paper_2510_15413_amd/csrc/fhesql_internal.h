@@ -154,6 +154,7 @@ struct tfhe_ctx {
     std::vector<Timed> timed;
     std::vector<hipEvent_t> event_pool;
     uint64_t t_launch[2] = {0, 0}, t_cts[2] = {0, 0};
+    std::vector<uint64_t> t_log;  // (kind << 32) | ciphertexts, per launch in order
     double t_ms[2] = {0, 0};
 };
 

@@ -1007,6 +1007,11 @@ extern "C" int sql_server_submit(sql_server* sv, const sql_sum_query* q, uint64_
     b.masked_sum(lev, q->rows, q->w, mask, dev(q->d_sum_col, (size_t)q->w * lw), (uint64_t)(uintptr_t)q->d_sum,
                  (uint64_t)(uintptr_t)c->d_false);
     sq->net = std::move(b.net);
+    for (const Level& L : sq->net.levels)
+        if (!L.lins.empty()) {  // the tick loop runs copies and gates only
+            delete sq;
+            return ctx_fail(c, TFHE_EINVAL, "server netlists must not contain linear steps");
+        }
     sq->tmp_bytes = al256(sq->net.tmp_words * b.wb);
     if (sv->fixed + sq->tmp_bytes > sv->budget) {
         delete sq;

@@ -113,7 +113,9 @@ def _oracle_rows(K, sc, sample, with_lt):
         m = C.eq(lz, list(sc["c1"][r]), list(sc["lit_eq"]))
         lt = C.lt(lz, list(sc["c1"][r]), list(sc["lit_lt"])) if with_lt else None
         roots.append((r, m, C.select(lz, m, list(sc["c2"][r])), lt))
-    C.evaluate(P, K, lz, threads=oracle.default_threads())
+    def progress(d, nd, g, ng):  # straight to the process stderr, past pytest's capture
+        print(f"oracle depth {d}/{nd}: {g}/{ng} gates", file=sys.__stderr__, flush=True)
+    C.evaluate(P, K, lz, threads=oracle.default_threads(), progress=progress)
     return roots
 
 
