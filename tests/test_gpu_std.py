@@ -113,9 +113,7 @@ def _oracle_rows(K, sc, sample, with_lt):
         m = C.eq(lz, list(sc["c1"][r]), list(sc["lit_eq"]))
         lt = C.lt(lz, list(sc["c1"][r]), list(sc["lit_lt"])) if with_lt else None
         roots.append((r, m, C.select(lz, m, list(sc["c2"][r])), lt))
-    def progress(d, nd, g, ng):  # straight to the process stderr, past pytest's capture
-        print(f"oracle depth {d}/{nd}: {g}/{ng} gates", file=sys.__stderr__, flush=True)
-    C.evaluate(P, K, lz, threads=oracle.default_threads(), progress=progress)
+    C.evaluate(P, K, lz, threads=oracle.default_threads())
     return roots
 
 
@@ -138,17 +136,24 @@ def test_std_scan_4096_rows(std, scan4096):
         assert np.array_equal(gm_lt[r], C.resolve(P, lt)), r
 
 
+def _sample64(rows):
+    sample = sorted(set(int(x) % rows for x in si.uniform_ints(si.DATA_SEED_BASE + 64, si.TAG_SHAPE, 63, 16)))
+    return sorted(set(sample) | {1234})[:64]
+
+
 @pytest.mark.slow
-def test_std_scan_64_row_sample(std, scan4096):
-    """64 seeded rows of the 4096-row step bit-exact end to end: the equality
-    mask, the masked select and the < mask of each (1,984 oracle
-    bootstraps, level-parallel on the host cores)."""
+@pytest.mark.parametrize("part", range(4))
+def test_std_scan_64_row_sample(std, scan4096, part):
+    """64 seeded rows of the 4096-row step bit-exact end to end, in four
+    parts of 16 rows: the equality mask, the masked select and the < mask of
+    each (1,984 oracle bootstraps in all, level-parallel on the host cores)."""
     K, _ = std
     sc = scan4096
-    sample = sorted(set(int(x) % sc["rows"] for x in si.uniform_ints(si.DATA_SEED_BASE + 64, si.TAG_SHAPE, 63, 16)))
-    sample = sorted(set(sample) | {1234})[:64]
-    say("oracle end to end on", len(sample), "seeded rows")
-    for r, m, sel, lt in _oracle_rows(K, sc, sample, True):
+    sample = _sample64(sc["rows"])
+    assert len(sample) == 64
+    part_rows = sample[16 * part:16 * (part + 1)]
+    say("oracle end to end on seeded rows", part_rows)
+    for r, m, sel, lt in _oracle_rows(K, sc, part_rows, True):
         assert np.array_equal(sc["m_eq"][r], C.resolve(P, m)), r
         assert np.array_equal(sc["s_eq"][r], C.resolve(P, sel)), r
         assert np.array_equal(sc["m_lt"][r], C.resolve(P, lt)), r
