@@ -253,10 +253,11 @@ def serve(args):
 def pbs64(args):
     """64-bit programmable bootstrapping (n=750, N=2048, l=4, Bg=2^6, KS 2^3x6):
     32-bit columns as 8 radix blocks of 4 bits.  mask(col1 < c) by block-wise
-    LUT comparison (4 levels) and the masked select of col2 (1 level) over a
-    row sample (--rows) of the 65,536-row table measure throughput; the masked
-    SUM mod 2^32 -- a row tree whose every level is 8 sequential block
-    levels -- is timed on the first --sum-rows selected rows."""
+    LUT comparison (4 levels) and the masked select of col2 (1 level) over
+    --rows rows of the 65,536-row table (all of it with --rows 65536, in
+    logged chunks of 4096 rows) measure throughput; the masked SUM mod 2^32 --
+    a row tree whose every level is 8 sequential block levels -- is timed on
+    the first --sum-rows selected rows."""
     import numpy as np
     import torch
     import seeded_inputs as si
@@ -289,16 +290,21 @@ def pbs64(args):
     torch.cuda.synchronize()
     log(f"pbs64 setup {time.perf_counter() - t_setup:.1f} s")
     ctx.timing_enable(True)
-    t0 = time.perf_counter()
-    ctx.sql_radix_mask_scan(c1, rows, nb, "lt", lit, mask)
-    torch.cuda.synchronize()
-    t_mask = time.perf_counter() - t0
-    log(f"pbs64 mask over {rows} rows: {t_mask:.2f} s")
-    t0 = time.perf_counter()
-    ctx.sql_radix_masked_select(mask, c2, rows, nb, sel)
-    torch.cuda.synchronize()
-    t_sel = time.perf_counter() - t0
-    log(f"pbs64 select: {t_sel:.2f} s")
+    # rows are independent: large tables run in chunks of 4096 rows, each
+    # logged, with the same output bits as one call
+    chunk = 4096
+    t_mask = t_sel = 0.0
+    for r0 in range(0, rows, chunk):
+        r1 = min(rows, r0 + chunk)
+        t0 = time.perf_counter()
+        ctx.sql_radix_mask_scan(c1[r0:r1], r1 - r0, nb, "lt", lit, mask[r0:r1])
+        torch.cuda.synchronize()
+        t_mask += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ctx.sql_radix_masked_select(mask[r0:r1], c2[r0:r1], r1 - r0, nb, sel[r0:r1])
+        torch.cuda.synchronize()
+        t_sel += time.perf_counter() - t0
+        log(f"pbs64 rows {r0}..{r1}: mask {t_mask:.2f} s, select {t_sel:.2f} s so far")
     br_n, br_ms, br_cts = ctx.timing_read("br")
     t0 = time.perf_counter()
     ctx.sql_radix_sum(sel[:srows].contiguous(), srows, nb, tot)
