@@ -12,8 +12,10 @@
  * implements that server path on one GPU with TFHE gate bootstrapping:
  *   bootstrap = blind rotation (gadget decomposition + GGSW x GLWE external
  *   products) -> sample extraction -> LWE key switching,
- * and boolean circuits of bootstrapped gates for =, <, >, BETWEEN, the
- * masked select and the masked SUM.
+ * and boolean circuits of bootstrapped gates for =, <, >, BETWEEN, whole
+ * WHERE expression trees (Section 4.3 B), the masked select and the masked
+ * SUM; programmable bootstrapping with look-up tables over radix-encoded
+ * 64-bit-torus integers; and a continuous-batching server for SUM queries.
  *
  * Conventions (all calls).
  *  - Torus values are uint32_t words when torus_bits = 32 and uint64_t words

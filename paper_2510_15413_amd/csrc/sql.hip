@@ -13,9 +13,11 @@
 //   SUM       : pairwise ripple-carry adder tree over rows in row order, the
 //               carry-out as new top bit, an odd operand zero-extended.
 // A netlist is a list of levels; a level is a list of strided segments
-// (one gate per row of a group).  Each level runs as three kernels over the
-// gates of every segment: linear combination, blind rotation + sample
-// extraction (MFMA or plain), key switching into the gate outputs.
+// (one gate per row of a group).  Each level runs device copies, then linear
+// steps without a bootstrap (expression trees' If-Then-Else sums and root
+// outputs), then three kernels over the gates of every segment: linear
+// combination, blind rotation + sample extraction (MFMA or plain), key
+// switching into the gate outputs.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
