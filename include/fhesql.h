@@ -299,6 +299,15 @@ void sql_server_destroy(sql_server* srv);
 /* Queue a query; its buffers must stay valid until it is done.  *id receives
  * its identifier.  Fails with TFHE_ENOMEM if it could never fit the budget. */
 int sql_server_submit(sql_server* srv, const sql_sum_query* q, uint64_t* id);
+/* Queue SELECT SUM(d_sum_col) WHERE <expression tree> over `rows` rows: the
+ * nodes (as in sql_expr_eval; the root must be a condition) are compiled at
+ * submission, so the node array may be freed on return, while the columns,
+ * literals, d_sum_col [rows][w][n+1] and d_sum (sum width of
+ * sql_masked_sum, [width][n+1]) must stay valid until the query is done.
+ * Errors as sql_expr_eval, TFHE_ENOMEM as sql_server_submit. */
+int sql_server_submit_expr(sql_server* srv, const void* const* d_cols, uint32_t ncols, uint32_t rows,
+                           uint32_t w, const sql_expr* nodes, uint32_t nnodes, const void* d_sum_col,
+                           void* d_sum, uint64_t* id);
 /* One tick on the stream (blocks until its kernels finish).  Outputs (any may
  * be NULL): gates run, active and queued query counts after the tick. */
 int sql_server_step(sql_server* srv, void* hip_stream, uint32_t* gates, uint32_t* active,

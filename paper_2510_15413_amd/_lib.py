@@ -34,7 +34,7 @@ EXPORTS = [
     "tfhe_lwe_encrypt", "tfhe_lwe_phase", "tfhe_timing_enable", "tfhe_timing_read",
     "tfhe_set_tuning", "sql_server_create", "sql_server_destroy", "sql_server_submit",
     "sql_server_step", "sql_server_done", "sql_server_bytes_in_use",
-    "sql_radix_mask_scan", "sql_radix_masked_select", "sql_radix_sum", "sql_expr_eval", "tfhe_timing_log",
+    "sql_radix_mask_scan", "sql_radix_masked_select", "sql_radix_sum", "sql_expr_eval", "tfhe_timing_log", "sql_server_submit_expr",
 ]
 # Expression-tree node kinds and comparison operators (sql_expr).
 SQL_EXPR_KINDS = {"column": 0, "const": 1, "literal": 2, "cmp": 3, "and": 4, "or": 5, "xor": 6, "not": 7,
@@ -117,6 +117,8 @@ def load():
         "sql_radix_masked_select": (i32, [vp, vp, vp, u32, u32, vp, vp]),
         "sql_radix_sum": (i32, [vp, vp, u32, u32, vp, vp]),
         "tfhe_timing_log": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), u64, ctypes.POINTER(u64)]),
+        "sql_server_submit_expr": (i32, [vp, ctypes.POINTER(vp), u32, u32, u32, ctypes.POINTER(SqlExpr), u32, vp, vp,
+                                         ctypes.POINTER(u64)]),
         "sql_expr_eval": (i32, [vp, ctypes.POINTER(vp), u32, u32, u32, ctypes.POINTER(SqlExpr), u32, vp, vp]),
         "tfhe_timing_read": (i32, [vp, i32, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(u64)]),
@@ -309,19 +311,7 @@ class Context:
         for i, t in enumerate(lits):
             _check_dev(t, f"lits[{i}]")
         _check_dev(out, "out")
-        arr = (SqlExpr * max(1, len(nodes)))()
-        for i, nd in enumerate(nodes):
-            kind = nd["kind"]
-            e = SqlExpr()
-            e.kind = SQL_EXPR_KINDS.get(kind, -1) if isinstance(kind, str) else int(kind)
-            e.op = SQL_CMP_OPS.get(nd.get("op"), -1) if isinstance(nd.get("op"), str) else int(nd.get("op", 0))
-            e.a, e.b, e.c = int(nd.get("a", -1)), int(nd.get("b", -1)), int(nd.get("c", -1))
-            e.col = int(nd.get("col", -1))
-            e.value = int(nd.get("value", 0)) & 0xFFFFFFFFFFFFFFFF
-            if kind == "literal":
-                e.d_lit = lits[nd["lit"]].data_ptr()
-            arr[i] = e
-        colp = (ctypes.c_void_p * max(1, len(cols)))(*[t.data_ptr() for t in cols])
+        arr, colp = _expr_arrays(nodes, cols, lits)
         self._rc(load().sql_expr_eval(self._h, colp, len(cols), rows, w, arr, len(nodes), _ptr(out),
                                       _stream(stream)), "sql_expr_eval")
 
@@ -338,6 +328,24 @@ class Context:
                                    q["sel_out"].data_ptr() if q.get("sel_out") is not None else None)
         self._rc(load().sql_scan_batch(self._h, arr, len(queries), 1 if use_graph else 0, _stream(stream)),
                  "sql_scan_batch")
+
+
+def _expr_arrays(nodes, cols, lits):
+    """ctypes arrays of an expression node list (dicts) and its columns."""
+    arr = (SqlExpr * max(1, len(nodes)))()
+    for i, nd in enumerate(nodes):
+        kind = nd["kind"]
+        e = SqlExpr()
+        e.kind = SQL_EXPR_KINDS.get(kind, -1) if isinstance(kind, str) else int(kind)
+        e.op = SQL_CMP_OPS.get(nd.get("op"), -1) if isinstance(nd.get("op"), str) else int(nd.get("op", 0))
+        e.a, e.b, e.c = int(nd.get("a", -1)), int(nd.get("b", -1)), int(nd.get("c", -1))
+        e.col = int(nd.get("col", -1))
+        e.value = int(nd.get("value", 0)) & 0xFFFFFFFFFFFFFFFF
+        if kind == "literal":
+            e.d_lit = lits[nd["lit"]].data_ptr()
+        arr[i] = e
+    colp = (ctypes.c_void_p * max(1, len(cols)))(*[t.data_ptr() for t in cols])
+    return arr, colp
 
 
 class Server:
@@ -370,6 +378,19 @@ class Server:
         qid = ctypes.c_uint64()
         self.ctx._rc(load().sql_server_submit(self._h, ctypes.byref(q), ctypes.byref(qid)), "sql_server_submit")
         self._keep[qid.value] = (col, sum_col, lit_a, lit_b, out)
+        return qid.value
+
+    def submit_expr(self, nodes, cols, rows, w, sum_col, out, lits=()):
+        """Queue SELECT SUM(sum_col) WHERE <expression tree> (nodes as in
+        Context.sql_expr_eval); returns the query id."""
+        for i, t in enumerate(list(cols) + list(lits) + [sum_col, out]):
+            _check_dev(t, f"tensor {i}")
+        arr, colp = _expr_arrays(nodes, cols, lits)
+        qid = ctypes.c_uint64()
+        self.ctx._rc(load().sql_server_submit_expr(self._h, colp, len(cols), rows, w, arr, len(nodes),
+                                                   sum_col.data_ptr(), out.data_ptr(), ctypes.byref(qid)),
+                     "sql_server_submit_expr")
+        self._keep[qid.value] = (tuple(cols), tuple(lits), sum_col, out)
         return qid.value
 
     def step(self, stream=None):

@@ -1,6 +1,7 @@
 """Client-side helpers on the device: bit encoding, seeded encryption and
-decryption of bit-wise encrypted integers (the client steps of Algorithm 1,
-EncryptQuery and Decrypt), built on the library's kernels."""
+decryption of bit-wise encrypted integers and the filtering of the returned
+rows (the client steps of Algorithm 1: EncryptQuery, Decrypt and
+FilterZeroRows), built on the library's kernels."""
 from __future__ import annotations
 
 import torch
@@ -42,3 +43,20 @@ def bits_to_values(bits: torch.Tensor) -> torch.Tensor:
     w = bits.shape[-1]
     sh = torch.arange(w, device=bits.device, dtype=torch.int64)
     return (bits.to(torch.int64) << sh).sum(-1)
+
+
+def decrypt_values(p, key, cts: torch.Tensor) -> torch.Tensor:
+    """Integers of bit-wise encrypted values [.., w, n+1] -> [..]."""
+    return bits_to_values(decrypt_bits(p, key, cts))
+
+
+def filter_zero_rows(p, key, selected: torch.Tensor):
+    """FilterZeroRows after Decrypt: the server returns If-Then-Else(mask, v,
+    enc(0)) for every row, so unmatched rows decrypt to zero.  selected:
+    [rows, w, n+1] (one column) or [rows, cols, w, n+1].  Returns (indices of
+    rows with a non-zero value in some column, their decrypted values)."""
+    vals = decrypt_values(p, key, selected)
+    if vals.dim() == 1:
+        vals = vals[:, None]
+    keep = (vals != 0).any(dim=1).nonzero().flatten()
+    return keep, vals[keep]

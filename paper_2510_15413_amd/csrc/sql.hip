@@ -813,16 +813,16 @@ extern "C" int sql_masked_sum(tfhe_ctx* c, const void* d_mask, const void* d_col
     return ex.run(b.net, false);
 }
 
-// Homomorphic expression tree (Section 4.3 B) over a table's columns.
-extern "C" int sql_expr_eval(tfhe_ctx* c, const void* const* d_cols, uint32_t ncols, uint32_t rows, uint32_t w,
-                             const sql_expr* nodes, uint32_t nnodes, void* d_out, void* stream) {
-    if (!c) return TFHE_EINVAL;
+namespace {
+
+// Checks an expression node list (operands precede their node, kinds and
+// types match, pointers present); isb[k] receives whether node k is boolean.
+int check_expr(tfhe_ctx* c, const void* const* d_cols, uint32_t ncols, uint32_t w, const sql_expr* nodes,
+               uint32_t nnodes, std::vector<char>& isb) {
     if (!nodes || !nnodes) return ctx_fail(c, TFHE_EINVAL, "empty expression");
     if (w < 1 || w > 64) return ctx_fail(c, TFHE_ESHAPE, "value width must be 1..64 bits");
-    if (!d_out) return ctx_fail(c, TFHE_EINVAL, "null output pointer");
     if (ncols && !d_cols) return ctx_fail(c, TFHE_EINVAL, "null column array");
-    // type check: every operand precedes its node and has the expected kind
-    std::vector<char> isb(nnodes, 0);
+    isb.assign(nnodes, 0);
     for (uint32_t k = 0; k < nnodes; k++) {
         const sql_expr& e = nodes[k];
         auto opnd = [&](int32_t i, bool want_bool) {
@@ -848,8 +848,13 @@ extern "C" int sql_expr_eval(tfhe_ctx* c, const void* const* d_cols, uint32_t nc
         isb[k] = e.kind == SQL_EXPR_CMP || e.kind == SQL_EXPR_AND || e.kind == SQL_EXPR_OR ||
                  e.kind == SQL_EXPR_XOR || e.kind == SQL_EXPR_NOT;
     }
-    if (!rows) return TFHE_OK;
-    Builder b(c);
+    return TFHE_OK;
+}
+
+// Adds the circuits of a checked node list to b's netlist and returns the
+// root's wires (not yet materialized).
+ExprVal compile_expr(Builder& b, const void* const* d_cols, uint32_t rows, uint32_t w, const sql_expr* nodes,
+                     uint32_t nnodes, const std::vector<char>& isb) {
     ExprCompiler ec{b, rows};
     const size_t lw = b.lw, wb = b.wb;
     std::vector<ExprVal> v(nnodes);
@@ -885,9 +890,26 @@ extern "C" int sql_expr_eval(tfhe_ctx* c, const void* const* d_cols, uint32_t nc
             case SQL_EXPR_ITE: o.bits = ec.ite(v[e.c].bits[0], v[e.a], v[e.b]).bits; break;
         }
     }
+    return v[nnodes - 1];
+}
+
+}  // namespace
+
+// Homomorphic expression tree (Section 4.3 B) over a table's columns.
+extern "C" int sql_expr_eval(tfhe_ctx* c, const void* const* d_cols, uint32_t ncols, uint32_t rows, uint32_t w,
+                             const sql_expr* nodes, uint32_t nnodes, void* d_out, void* stream) {
+    if (!c) return TFHE_EINVAL;
+    if (!d_out) return ctx_fail(c, TFHE_EINVAL, "null output pointer");
+    std::vector<char> isb;
+    int rc = check_expr(c, d_cols, ncols, w, nodes, nnodes, isb);
+    if (rc) return rc;
+    if (!rows) return TFHE_OK;
+    Builder b(c);
+    const ExprVal root = compile_expr(b, d_cols, rows, w, nodes, nnodes, isb);
     // the root's bits are written to d_out by linear steps (exact copies,
     // negations or trivial encryptions)
-    const ExprVal& root = v[nnodes - 1];
+    ExprCompiler ec{b, rows};
+    const size_t lw = b.lw, wb = b.wb;
     for (size_t j = 0; j < root.bits.size(); j++) {
         const Ref o = root.is_bool ? dev(d_out, lw)
                                    : Ref{(uint64_t)(uintptr_t)d_out + (uint64_t)j * lw * wb, (int64_t)((size_t)w * lw)};
@@ -994,6 +1016,19 @@ extern "C" void sql_server_destroy(sql_server* sv) {
 
 extern "C" size_t sql_server_bytes_in_use(const sql_server* sv) { return sv ? sv->in_use : 0; }
 
+static int server_enqueue(sql_server* sv, ServerQuery* sq, size_t wb, uint64_t* id) {
+    sq->tmp_bytes = al256(sq->net.tmp_words * wb);
+    if (sv->fixed + sq->tmp_bytes > sv->budget) {
+        delete sq;
+        return ctx_fail(sv->c, TFHE_ENOMEM, "query working set exceeds the HBM budget");
+    }
+    sq->id = sv->next_id++;
+    sv->known.insert(sq->id);
+    sv->queue.push_back(sq);
+    *id = sq->id;
+    return TFHE_OK;
+}
+
 extern "C" int sql_server_submit(sql_server* sv, const sql_sum_query* q, uint64_t* id) {
     if (!sv || !q || !id) return TFHE_EINVAL;
     tfhe_ctx* c = sv->c;
@@ -1009,21 +1044,31 @@ extern "C" int sql_server_submit(sql_server* sv, const sql_sum_query* q, uint64_
     b.masked_sum(lev, q->rows, q->w, mask, dev(q->d_sum_col, (size_t)q->w * lw), (uint64_t)(uintptr_t)q->d_sum,
                  (uint64_t)(uintptr_t)c->d_false);
     sq->net = std::move(b.net);
-    for (const Level& L : sq->net.levels)
-        if (!L.lins.empty()) {  // the tick loop runs copies and gates only
-            delete sq;
-            return ctx_fail(c, TFHE_EINVAL, "server netlists must not contain linear steps");
-        }
-    sq->tmp_bytes = al256(sq->net.tmp_words * b.wb);
-    if (sv->fixed + sq->tmp_bytes > sv->budget) {
-        delete sq;
-        return ctx_fail(c, TFHE_ENOMEM, "query working set exceeds the HBM budget");
-    }
-    sq->id = sv->next_id++;
-    sv->known.insert(sq->id);
-    sv->queue.push_back(sq);
-    *id = sq->id;
-    return TFHE_OK;
+    return server_enqueue(sv, sq, b.wb, id);
+}
+
+// SELECT SUM(sum_col) WHERE <expression tree>: the tree's boolean root is
+// the mask of the same masked SUM circuit.
+extern "C" int sql_server_submit_expr(sql_server* sv, const void* const* d_cols, uint32_t ncols, uint32_t rows,
+                                      uint32_t w, const sql_expr* nodes, uint32_t nnodes, const void* d_sum_col,
+                                      void* d_sum, uint64_t* id) {
+    if (!sv || !id) return TFHE_EINVAL;
+    tfhe_ctx* c = sv->c;
+    if (!d_sum_col || !d_sum || !rows || w > 32) return ctx_fail(c, TFHE_EINVAL, "bad SUM query");
+    std::vector<char> isb;
+    int rc = check_expr(c, d_cols, ncols, w, nodes, nnodes, isb);
+    if (rc) return rc;
+    if (!isb[nnodes - 1]) return ctx_fail(c, TFHE_EINVAL, "the WHERE expression must be a condition");
+    Builder b(c);
+    const ExprVal root = compile_expr(b, d_cols, rows, w, nodes, nnodes, isb);
+    ExprCompiler ec{b, rows};
+    const Ref mask = b.tmp(rows);
+    const Wire m = ec.lin({{&root.bits[0], 1}}, 0, &mask);
+    b.masked_sum(m.rg, rows, w, mask, dev(d_sum_col, (size_t)w * b.lw), (uint64_t)(uintptr_t)d_sum,
+                 (uint64_t)(uintptr_t)c->d_false);
+    auto* sq = new ServerQuery();
+    sq->net = std::move(b.net);
+    return server_enqueue(sv, sq, b.wb, id);
 }
 
 static int server_admit(sql_server* sv) {
@@ -1035,10 +1080,11 @@ static int server_admit(sql_server* sv) {
         const uint64_t base = (uint64_t)(uintptr_t)q->tmp;
         auto res = [&](uint64_t a) { return (a & REL) ? base + (a & ~REL) : a; };
         for (auto& L : q->net.levels) {
-            for (auto& sg : L.segs) {
-                for (int j = 0; j < sg.nin; j++) sg.in[j] = res(sg.in[j]);
-                sg.out = res(sg.out);
-            }
+            for (auto* group : {&L.segs, &L.lins})
+                for (auto& sg : *group) {
+                    for (int j = 0; j < sg.nin; j++) sg.in[j] = res(sg.in[j]);
+                    sg.out = res(sg.out);
+                }
             for (auto& cp : L.copies) { cp.src = res(cp.src); cp.dst = res(cp.dst); }
         }
         sv->in_use += q->tmp_bytes;
@@ -1058,15 +1104,18 @@ extern "C" int sql_server_step(sql_server* sv, void* stream, uint32_t* gates, ui
     size_t nseg = 0;
     uint32_t total = 0;
     std::vector<Copy> copies;
+    std::vector<Segment> lins;  // run after the copies, before the gates
     for (auto* q : sv->active) {
-        if (total >= sv->max_batch || nseg >= kSegCap) break;
+        if (total >= sv->max_batch || nseg + lins.size() >= kSegCap) break;
         if (q->level >= q->net.levels.size()) continue;
         Level& L = q->net.levels[q->level];
         if (!q->copies_done) {
+            if (nseg + lins.size() + L.lins.size() >= kSegCap) break;  // the next tick takes this query's level
             copies.insert(copies.end(), L.copies.begin(), L.copies.end());
+            lins.insert(lins.end(), L.lins.begin(), L.lins.end());
             q->copies_done = true;
         }
-        while (q->seg < L.segs.size() && total < sv->max_batch && nseg < kSegCap) {
+        while (q->seg < L.segs.size() && total < sv->max_batch && nseg + lins.size() < kSegCap) {
             Segment sg = L.segs[q->seg];
             const uint32_t take = std::min<uint32_t>(sg.rows - q->row, sv->max_batch - total);
             for (int j = 0; j < sg.nin; j++) sg.in[j] += (uint64_t)(q->row * sg.in_stride[j]) * wb;
@@ -1089,6 +1138,21 @@ extern "C" int sql_server_step(sql_server* sv, void* stream, uint32_t* gates, ui
         rc = hip_check(c, hipMemcpyAsync((void*)(uintptr_t)cp.dst, (const void*)(uintptr_t)cp.src, cp.bytes,
                                          hipMemcpyDeviceToDevice, s), "server copy");
         if (rc) return rc;
+    }
+    if (!lins.empty()) {  // linear steps go after the gate segments in the staging arrays
+        uint32_t lt = 0;
+        for (size_t k = 0; k < lins.size(); k++) {
+            sv->hsegs[nseg + k] = lins[k];
+            sv->hstart[nseg + k] = lt;
+            lt += lins[k].rows;
+        }
+        const size_t nl = lins.size();
+        if ((rc = hip_check(c, hipMemcpyAsync(sv->dsegs + nseg, sv->hsegs + nseg, nl * sizeof(Segment),
+                                              hipMemcpyHostToDevice, s), "server linear steps")) ||
+            (rc = hip_check(c, hipMemcpyAsync(sv->dstart + nseg, sv->hstart + nseg, nl * 4, hipMemcpyHostToDevice, s),
+                            "server linear starts")) ||
+            (rc = launch_lin(c, sv->dsegs + nseg, sv->dstart + nseg, (int)nl, lt, s)))
+            return rc;
     }
     if (total) {
         if ((rc = hip_check(c, hipMemcpyAsync(sv->dsegs, sv->hsegs, nseg * sizeof(Segment), hipMemcpyHostToDevice, s),

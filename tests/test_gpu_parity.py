@@ -382,3 +382,88 @@ def test_server_isolation_parity_and_admission():
         assert np.array_equal(tight[i], alone[i]), i
     with pytest.raises(fs.FheError):
         fs.Server(ctx, 1024, max_batch=64)
+
+
+def test_client_decrypt_and_filter_zero_rows():
+    """Algorithm 1's client end: decrypt the server's selected rows on the
+    device and drop the zero rows; what remains is exactly the matching rows
+    with a non-zero value."""
+    from paper_2510_15413_amd import client
+    p = si.TOY
+    K = keys_for("toy")
+    ctx = ctx_for("toy")
+    rows, w = 24, 4
+    col1, col2, c1, c2 = _table(p, K, rows, w, 40)
+    c = int(col1[5])
+    lit = _lit(p, K, c, w, 41)
+    mask, sel = empty(p, rows, p.n + 1), empty(p, rows, w, p.n + 1)
+    ctx.sql_mask_scan(to_dev(p, c1), rows, w, "eq", to_dev(p, lit), mask)
+    ctx.sql_masked_select(mask, to_dev(p, c2), rows, w, sel)
+    torch.cuda.synchronize()
+    key = to_dev(p, K.s)
+    idx, vals = client.filter_zero_rows(p, key, sel)
+    want = [r for r in range(rows) if col1[r] == c and col2[r] != 0]
+    assert idx.cpu().tolist() == want
+    assert vals[:, 0].cpu().tolist() == [int(col2[r]) for r in want]
+    assert client.decrypt_values(p, key, to_dev(p, c2)).cpu().tolist() == [int(v) for v in col2]
+
+
+def test_server_expression_queries():
+    """SELECT SUM(col) WHERE <expression tree> through the server: the same
+    bits alone, mixed with single-predicate queries, and through the direct
+    calls (sql_expr_eval, then sql_masked_sum); oracle end to end for one
+    query and decrypted truth for all."""
+    p = si.TINY
+    K = keys_for("tiny")
+    ctx = ctx_for("tiny")
+    w, rows = 4, 9
+    vals = si.uniform_ints(si.DATA_SEED_BASE + 4200, si.TAG_DATA, 3 * rows, w).reshape(3, rows)
+    cts = [enc_bits(p, K, si.column_bits(vals[k], w), 4210 + k).reshape(rows, w, p.n + 1) for k in range(3)]
+    dcols = [to_dev(p, c) for c in cts]
+    lit = _lit(p, K, 6, w, 4220).reshape(w, p.n + 1)
+    trees = [
+        [{"kind": "column", "col": 0}, {"kind": "literal", "lit": 0}, {"kind": "cmp", "op": "gt", "a": 0, "b": 1},
+         {"kind": "column", "col": 1}, {"kind": "const", "value": 10}, {"kind": "cmp", "op": "lt", "a": 3, "b": 4},
+         {"kind": "and", "a": 2, "b": 5}],
+        [{"kind": "column", "col": 0}, {"kind": "column", "col": 1}, {"kind": "max", "a": 0, "b": 1},
+         {"kind": "const", "value": 12}, {"kind": "cmp", "op": "le", "a": 2, "b": 3}, {"kind": "not", "a": 4}],
+        [{"kind": "column", "col": 1}, {"kind": "const", "value": 3}, {"kind": "cmp", "op": "ne", "a": 0, "b": 1}],
+    ]
+    width = fs.sum_width(w, rows)
+
+    def run_server(which, stagger):
+        srv = fs.Server(ctx, 1 << 34, max_batch=64)
+        outs, ids, pending, ticks = {}, {}, list(which), 0
+        while pending or any(not srv.done(ids[i]) for i in ids):
+            if pending and ticks % stagger == 0:
+                i = pending.pop(0)
+                outs[i] = empty(p, width, p.n + 1)
+                if i < len(trees):
+                    ids[i] = srv.submit_expr(trees[i], dcols, rows, w, dcols[2], outs[i], lits=[to_dev(p, lit)])
+                else:  # a single-predicate query in the mix
+                    ids[i] = srv.submit(dcols[0], dcols[2], rows, w, "lt", to_dev(p, lit), outs[i])
+            srv.step()
+            ticks += 1
+            assert ticks < 5000
+        srv.close()
+        return {i: from_dev(p, outs[i]) for i in outs}
+
+    alone = {}
+    for i in range(len(trees)):
+        alone.update(run_server([i], 1))
+    mixed = run_server([3, 0, 1, 2], 2)
+    for i in range(len(trees)):
+        assert np.array_equal(alone[i], mixed[i]), i
+        # direct calls
+        m, s_dir = empty(p, rows, p.n + 1), empty(p, width, p.n + 1)
+        ctx.sql_expr_eval(trees[i], dcols, rows, w, m, lits=[to_dev(p, lit)])
+        ctx.sql_masked_sum(m, dcols[2], rows, w, s_dir)
+        torch.cuda.synchronize()
+        assert np.array_equal(from_dev(p, s_dir), alone[i]), i
+        pred = [C.expr_plain(trees[i], [int(vals[0][r]), int(vals[1][r])], [6], w) for r in range(rows)]
+        assert bits_to_int(dec_bits(p, K, alone[i])) == sum(int(vals[2][r]) for r in range(rows) if pred[r]), i
+    # oracle end to end for the first tree
+    masks = C.expr_rows(p, K, trees[0], [cts[0], cts[1]], [lit], w)
+    be = C.CipherBackend(p, K)
+    sel = [C.select(be, masks[r], list(cts[2][r])) for r in range(rows)]
+    assert np.array_equal(alone[0], np.stack(C.sum_tree(be, sel)))
