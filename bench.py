@@ -107,16 +107,21 @@ def counter_traffic():
     return prof
 
 
+def param_desc(p):
+    return f"{p.name} q={p.q} n={p.n} N={p.N} l={p.l} Bg=2^{p.bg_bits} ks 2^{p.ks_bits}x{p.ks_t}"
+
+
 def batch16(args):
     """16 tables with log-uniform row counts in [100, 65536] and 16-bit
     columns, each with one predicate (==, <, BETWEEN) and the masked select of
-    its second column, at the toy parameter set, all tables' gates merged
-    level by level and captured in one HIP graph."""
+    its second column, all tables' gates merged level by level and captured
+    in one HIP graph; toy parameters by default, --params std for the
+    standard gate set."""
     import torch
     import seeded_inputs as si
     import paper_2510_15413_amd as fs
     from paper_2510_15413_amd import client, autotune
-    p = si.TOY
+    p = si.PARAMS[args.params]
     w = 16
     seed = si.DATA_SEED_BASE + 3
     rows_t, ops_t = si.uneven_tables(seed)
@@ -174,7 +179,7 @@ def batch16(args):
     ok = all(bool((client.decrypt_bits(p, s, q["mask"]).cpu().numpy() == tr).all()) for q, tr in zip(queries, truths))
     ops_bs = int8_ops_per_bootstrap(p)
     ach = br_cts * ops_bs / (br_ms * 1e-3) / 1e12 if br_ms > 0 else 0.0
-    res = {"workload": "batch16", "params": "toy n=64 N=256 l=2 Bg=2^8", "tables": len(queries),
+    res = {"workload": "batch16", "params": param_desc(p), "tables": len(queries),
            "rows": int(rows_t.sum()), "rows_per_table": rows_t.tolist(), "ops": [names[o] for o in ops_t.tolist()],
            "bootstraps_per_run": bs_total, "runs": args.steps, "seconds_per_run": round(wall / args.steps, 4),
            "bootstraps_per_s": round(bs_total * args.steps / wall, 1),
@@ -188,13 +193,14 @@ def batch16(args):
 
 def serve(args):
     """Open-loop Poisson arrivals of SELECT SUM(col2) WHERE col1 op c over a
-    prefix of one resident table (toy parameters, 8-bit columns), prefix
-    lengths log-uniform in [1e3, max_rows], op uniform over {==, <, >}."""
+    prefix of one resident table (8-bit columns; toy parameters by default,
+    --params std for the standard gate set), prefix lengths log-uniform in
+    [1e3, max_rows], op uniform over {==, <, >}."""
     import torch
     import seeded_inputs as si
     import paper_2510_15413_amd as fs
     from paper_2510_15413_amd import client, serve as srv
-    p = si.TOY
+    p = si.PARAMS[args.params]
     w = 8
     seed = si.DATA_SEED_BASE + 5
     s, S, bsk, ksk = fs.tfhe_keygen(p, si.KEY_SEED_BASE + 5)
@@ -246,7 +252,7 @@ def serve(args):
         log(f"serve lambda={lam}: p50 {summ['p50_s']:.2f} s p99 {summ['p99_s']:.2f} s "
             f"{summ['rows_per_s']:.0f} rows/s ok={ok}")
     ctx.close()
-    print(json.dumps({"workload": "serve", "params": "toy n=64 N=256 l=2 Bg=2^8", "bits": w,
+    print(json.dumps({"workload": "serve", "params": param_desc(p), "bits": w,
                       "table_rows": R, "hbm_budget_bytes": budget, "rates": results}), flush=True)
 
 
@@ -456,6 +462,8 @@ def main():
                     help="std: the headline 4096-row scan; batch16: 16 uneven tables at toy "
                          "parameters in one level-batched hipGraph schedule")
     ap.add_argument("--autotune", action="store_true", help="batch16: tune the executor knobs first")
+    ap.add_argument("--params", default="toy", choices=["toy", "std"],
+                    help="batch16 and serve: TFHE parameter set")
     ap.add_argument("--rates", default="1,2,4,8,16,32,64", help="serve: Poisson rates (queries/s)")
     ap.add_argument("--queries", type=int, default=16, help="serve: queries per rate")
     ap.add_argument("--max-rows", type=int, default=1 << 20, help="serve: largest table prefix")

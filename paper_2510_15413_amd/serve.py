@@ -55,6 +55,8 @@ def run(ctx, queries, arrivals, budget_bytes, max_batch=65536, log=None, timeout
             if srv.done(ids[i]):
                 done_at[i] = now
                 pending.discard(i)
+                if log:
+                    log(f"query {i} ({queries[i]['rows']} rows) done at {now:.2f} s")
         if now > timeout_s:
             raise RuntimeError("serving run exceeded its time limit")
     makespan = time.perf_counter() - t0
