@@ -113,7 +113,12 @@ int tfhe_set_kernel(tfhe_ctx* ctx, int kind);
  *                        (u,p) block at a time; 1 = one block at a time;
  *                        2 = pairs when l is even and they fit, else one;
  *                        3 = all blocks of a step, accumulator in global
- *                        memory, when they fit. */
+ *                        memory, when they fit.
+ * The blind-rotation workspace depends on the row pass and digit grouping
+ * (several passes with per-group digits add a digit cache).  Direct calls and
+ * the level executor size it per call; a server sizes it at creation, and a
+ * later tuning that needs more makes sql_server_step return TFHE_EINVAL
+ * without launching (restore the tuning, or create a new server). */
 #define TFHE_TUNE_DIGIT_BLOCKS 3
 int tfhe_set_tuning(tfhe_ctx* ctx, int key, int64_t value);
 

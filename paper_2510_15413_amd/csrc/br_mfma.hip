@@ -43,6 +43,7 @@ struct BrArgs {
     const int32_t* tv_index;  // [B] or null
     void* out;                // [B][N+1] words
     void* ws;                 // [grid][2][2N*16] words
+    int8_t* dcache;           // [grid][2l][N/64][1024] digit bytes (several row passes) or null
     int B, n, l, bg_bits;
 };
 
@@ -59,10 +60,11 @@ FHE_DEV size_t acc_idx(int N, int v, int j, int c) {
 // A work item is 4 consecutive coefficients of one ciphertext: its own 4
 // words are one 16-byte group of the accumulator layout and the 4 rotated
 // words straddle at most two such groups, so an item takes three vector
-// loads; the loads of G items are issued together.
-template <typename T, int R, int U>
+// loads; the loads of G items are issued together.  With GC the packed
+// digits are also written to gdst at the same offsets (the digit cache).
+template <typename T, int R, int U, bool GC = false>
 FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u_lo, int p_lo, int p_n, int l,
-                          int bgb) {
+                          int bgb, int8_t* gdst = nullptr) {
     typedef T vec4 __attribute__((ext_vector_type(4)));
     constexpr int N = R * 64;
     constexpr int NG = N / 4;  // 4-word groups per component
@@ -134,7 +136,9 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
                     packed |= ((uint32_t)(d & 0xFF)) << (8 * e);
                 }
                 const int blk = (u - u_lo) * p_n + (p - p_lo);
-                *(uint32_t*)(dbuf + ((size_t)blk * R + ch) * 1024 + (g * 16 + c) * 16 + bo) = packed;
+                const size_t o = ((size_t)blk * R + ch) * 1024 + (g * 16 + c) * 16 + bo;
+                *(uint32_t*)(dbuf + o) = packed;
+                if (GC) *(uint32_t*)(gdst + o) = packed;
             }
         }
     }
@@ -238,6 +242,12 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     constexpr bool DOUBLE = DALL;
     constexpr int NPASS = R / RP;
     static_assert(!ACCL || NPASS == 1, "LDS accumulator mode needs one row pass");
+    // Several row passes with digits formed per group: the first pass also
+    // writes each group's digits to a per-workgroup global cache (L2
+    // resident) and the later passes of the step copy them back to LDS.
+    constexpr bool DCACHE = !DALL && NPASS > 1;
+    constexpr int DCU = (DALL ? 1 : DG) * R * 64;  // uint4 per digit group
+    constexpr int DCV = (DCU + THREADS - 1) / THREADS;
     const int n = a.n, l = a.l, NB = 2 * l;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int ct0 = blockIdx.x * CTS;
@@ -348,7 +358,24 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
                     else digits_phase<T, R, 1>(acc1, ab, dbuf, 0, 0, l, l, a.bg_bits);
                     __syncthreads();
                 }
-                if (!DALL && ub % DG == 0) digits_phase<T, R, 1>(src, ab, dbuf, ub / l, ub % l, DG, l, a.bg_bits);
+                if (!DALL && ub % DG == 0) {
+                    int8_t* gc = DCACHE ? a.dcache + ((size_t)blockIdx.x * NB + ub) * R * 1024 : nullptr;
+                    if (!DCACHE || pass == 0) {
+                        digits_phase<T, R, 1, DCACHE>(src, ab, dbuf, ub / l, ub % l, DG, l, a.bg_bits, gc);
+                    } else {
+                        uint4 dc[DCV];
+#pragma unroll
+                        for (int q = 0; q < DCV; q++) {
+                            const int idx = tid + q * THREADS;
+                            if (DCU % THREADS == 0 || idx < DCU) dc[q] = ((const uint4*)gc)[idx];
+                        }
+#pragma unroll
+                        for (int q = 0; q < DCV; q++) {
+                            const int idx = tid + q * THREADS;
+                            if (DCU % THREADS == 0 || idx < DCU) ((uint4*)dbuf)[idx] = dc[q];
+                        }
+                    }
+                }
                 if (DOUBLE) {
                     // prefetch the next block of the (i, pass, ub) sequence
                     int ni = i, nub = ub + 1, npass = pass;
@@ -447,24 +474,67 @@ size_t lds_need(const tfhe_ctx* c, int dg) {
     return b;
 }
 
+constexpr int kNoFit = -100;
+
+// Row tiles per pass instantiated for (q, N) and the row_pass knob.
+int plan_rp(const tfhe_ctx* c) {
+    const int N = (int)c->p.N, rp = c->row_pass;
+    if (c->q == 32) {
+        switch (N) {
+            case 64: return 1;
+            case 256: return rp == 2 ? 2 : 4;
+            case 512: return rp == 4 ? 4 : 8;
+            case 1024: return rp == 8 ? 8 : 16;
+            case 2048: return 8;
+        }
+    } else {
+        switch (N) {
+            case 64: return 1;
+            case 256: case 512: case 1024: return 4;
+            case 2048: return rp == 4 ? 4 : 8;
+        }
+    }
+    return 0;
+}
+
 // Largest digit grouping that fits LDS and the digit_blocks knob (0 auto,
 // 1 one block, 2 pairs of levels when l is even, 3 all blocks of a step with
 // the accumulator in global memory).  Auto prefers, with one row pass, the
 // per-component grouping that keeps accumulator component 0 in LDS.
-template <typename T, int R, int RP>
-int dispatch_dg(tfhe_ctx* c, const BrArgs& a, hipStream_t s) {
+int plan_dg(const tfhe_ctx* c, int R, int rp) {
     const size_t max_lds = (size_t)c->prop.maxSharedMemoryPerMultiProcessor > 0
                                ? (size_t)c->prop.maxSharedMemoryPerMultiProcessor
                                : (size_t)160 * 1024;
+    if (rp == R && c->digit_blocks == 0 && lds_need(c, -1) <= max_lds) return -1;
+    if ((c->digit_blocks == 0 || c->digit_blocks == 3) && lds_need(c, 0) <= max_lds) return 0;
+    if (c->digit_blocks != 1 && c->p.l % 2 == 0 && lds_need(c, 2) <= max_lds) return 2;
+    if (lds_need(c, 1) > max_lds) return kNoFit;
+    return 1;
+}
+
+template <typename T, int R, int RP>
+int dispatch_dg(tfhe_ctx* c, const BrArgs& a, int dg, hipStream_t s) {
     if constexpr (RP == R) {
-        if (c->digit_blocks == 0 && lds_need(c, -1) <= max_lds) return launch_t<T, R, RP, -1>(c, a, lds_need(c, -1), s);
+        if (dg == -1) return launch_t<T, R, RP, -1>(c, a, lds_need(c, -1), s);
     }
-    if ((c->digit_blocks == 0 || c->digit_blocks == 3) && lds_need(c, 0) <= max_lds)
-        return launch_t<T, R, RP, 0>(c, a, lds_need(c, 0), s);
-    if (c->digit_blocks != 1 && c->p.l % 2 == 0 && lds_need(c, 2) <= max_lds)
-        return launch_t<T, R, RP, 2>(c, a, lds_need(c, 2), s);
-    if (lds_need(c, 1) > max_lds) return ctx_fail(c, TFHE_EINVAL, "parameters exceed LDS capacity of the MFMA kernel");
-    return launch_t<T, R, RP, 1>(c, a, lds_need(c, 1), s);
+    if (dg == 0) return launch_t<T, R, RP, 0>(c, a, lds_need(c, 0), s);
+    if (dg == 2) return launch_t<T, R, RP, 2>(c, a, lds_need(c, 2), s);
+    if (dg == 1) return launch_t<T, R, RP, 1>(c, a, lds_need(c, 1), s);
+    return ctx_fail(c, TFHE_EINVAL, "parameters exceed LDS capacity of the MFMA kernel");
+}
+
+// Accumulator buffers, then (several row passes with per-group digits) the
+// digit cache.
+size_t acc_ws_bytes(const tfhe_ctx* c, uint32_t B) {
+    const size_t grid = (B + CTS - 1) / CTS;
+    return grid * 2 * 2 * (size_t)c->p.N * CTS * word_bytes(c);
+}
+
+size_t dcache_bytes(const tfhe_ctx* c, uint32_t B) {
+    const int R = (int)c->p.N / 64, rp = plan_rp(c);
+    if (rp <= 0 || R / rp <= 1 || plan_dg(c, R, rp) <= 0) return 0;
+    const size_t grid = (B + CTS - 1) / CTS;
+    return grid * 2 * (size_t)c->p.l * R * 1024;
 }
 
 }  // namespace
@@ -482,13 +552,18 @@ bool mfma_row_pass_supported(const tfhe_ctx* c, int rp) {
     return false;
 }
 
-size_t mfma_ws_bytes(const tfhe_ctx* c, uint32_t B) {
-    const size_t grid = (B + CTS - 1) / CTS;
-    return grid * 2 * 2 * (size_t)c->p.N * CTS * word_bytes(c);
-}
+size_t mfma_ws_bytes(const tfhe_ctx* c, uint32_t B) { return acc_ws_bytes(c, B) + dcache_bytes(c, B); }
 
 int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_t* tv_index,
-                   void* big_out, uint32_t B, void* ws, hipStream_t s) {
+                   void* big_out, uint32_t B, void* ws, size_t ws_cap, hipStream_t s) {
+    const int N = (int)c->p.N;
+    const int rp = plan_rp(c);
+    if (N < 64 || rp <= 0) return ctx_fail(c, TFHE_EINVAL, "unsupported N for the MFMA kernel");
+    const int dg = plan_dg(c, N / 64, rp);
+    if (dg == kNoFit) return ctx_fail(c, TFHE_EINVAL, "parameters exceed LDS capacity of the MFMA kernel");
+    // the tuning may have changed since the workspace was sized
+    if (!ws || mfma_ws_bytes(c, B) > ws_cap)
+        return ctx_fail(c, TFHE_EINVAL, "blind-rotation workspace too small for the current tuning");
     BrArgs a;
     a.lwe = lwe_in;
     a.bsk8 = c->d_bsk8;
@@ -496,28 +571,28 @@ int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_
     a.tv_index = tv_index;
     a.out = big_out;
     a.ws = ws;
+    a.dcache = dcache_bytes(c, B) ? (int8_t*)ws + acc_ws_bytes(c, B) : nullptr;
     a.B = (int)B;
     a.n = (int)c->p.n;
     a.l = (int)c->p.l;
     a.bg_bits = (int)c->p.bg_bits;
-    const int N = (int)c->p.N;
-    const int rp = c->row_pass;
     if (c->q == 32) {
         switch (N) {
-            case 64: return dispatch_dg<uint32_t, 1, 1>(c, a, s);
-            case 256: return rp == 2 ? dispatch_dg<uint32_t, 4, 2>(c, a, s) : dispatch_dg<uint32_t, 4, 4>(c, a, s);
-            case 512: return rp == 4 ? dispatch_dg<uint32_t, 8, 4>(c, a, s) : dispatch_dg<uint32_t, 8, 8>(c, a, s);
-            case 1024: return rp == 8 ? dispatch_dg<uint32_t, 16, 8>(c, a, s) : dispatch_dg<uint32_t, 16, 16>(c, a, s);
-            case 2048: return dispatch_dg<uint32_t, 32, 8>(c, a, s);
+            case 64: return dispatch_dg<uint32_t, 1, 1>(c, a, dg, s);
+            case 256: return rp == 2 ? dispatch_dg<uint32_t, 4, 2>(c, a, dg, s) : dispatch_dg<uint32_t, 4, 4>(c, a, dg, s);
+            case 512: return rp == 4 ? dispatch_dg<uint32_t, 8, 4>(c, a, dg, s) : dispatch_dg<uint32_t, 8, 8>(c, a, dg, s);
+            case 1024:
+                return rp == 8 ? dispatch_dg<uint32_t, 16, 8>(c, a, dg, s) : dispatch_dg<uint32_t, 16, 16>(c, a, dg, s);
+            case 2048: return dispatch_dg<uint32_t, 32, 8>(c, a, dg, s);
         }
     } else {
         switch (N) {
-            case 64: return dispatch_dg<uint64_t, 1, 1>(c, a, s);
-            case 256: return dispatch_dg<uint64_t, 4, 4>(c, a, s);
-            case 512: return dispatch_dg<uint64_t, 8, 4>(c, a, s);
-            case 1024: return dispatch_dg<uint64_t, 16, 4>(c, a, s);
+            case 64: return dispatch_dg<uint64_t, 1, 1>(c, a, dg, s);
+            case 256: return dispatch_dg<uint64_t, 4, 4>(c, a, dg, s);
+            case 512: return dispatch_dg<uint64_t, 8, 4>(c, a, dg, s);
+            case 1024: return dispatch_dg<uint64_t, 16, 4>(c, a, dg, s);
             case 2048:
-                return rp == 4 ? dispatch_dg<uint64_t, 32, 4>(c, a, s) : dispatch_dg<uint64_t, 32, 8>(c, a, s);
+                return rp == 4 ? dispatch_dg<uint64_t, 32, 4>(c, a, dg, s) : dispatch_dg<uint64_t, 32, 8>(c, a, dg, s);
         }
     }
     return ctx_fail(c, TFHE_EINVAL, "unsupported N for the MFMA kernel");

@@ -6,7 +6,7 @@
 #include "fhesql_internal.h"
 
 int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_t* tv_index,
-                   void* big_out, uint32_t B, void* ws, hipStream_t s);
+                   void* big_out, uint32_t B, void* ws, size_t ws_cap, hipStream_t s);
 int launch_br_plain(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_t* tv_index,
                     void* big_out, uint32_t B, hipStream_t s);
 size_t mfma_ws_bytes(const tfhe_ctx* c, uint32_t B);
@@ -304,12 +304,12 @@ size_t blind_rotate_ws_bytes(const tfhe_ctx* c, uint32_t B) {
 }
 
 int launch_blind_rotate(tfhe_ctx* c, const void* lwe_in, const void* testv_table, const int32_t* tv_index,
-                        void* big_out, uint32_t B, void* ws, hipStream_t s) {
+                        void* big_out, uint32_t B, void* ws, size_t ws_cap, hipStream_t s) {
     if (B == 0) return TFHE_OK;
     const void* tv = testv_table ? testv_table : c->d_gate_tv;
     TimedLaunch tl(c, s, 0, B);
     if (c->kernel == TFHE_KERNEL_PLAIN) return launch_br_plain(c, lwe_in, tv, tv_index, big_out, B, s);
-    return launch_br_mfma(c, lwe_in, tv, tv_index, big_out, B, ws, s);
+    return launch_br_mfma(c, lwe_in, tv, tv_index, big_out, B, ws, ws_cap, s);
 }
 
 extern "C" int tfhe_bootstrap_batch(tfhe_ctx* c, const void* d_lwe_in, const void* d_testv, void* d_out,
@@ -325,7 +325,7 @@ extern "C" int tfhe_bootstrap_batch(tfhe_ctx* c, const void* d_lwe_in, const voi
         if (rc) return rc;
         if ((rc = ctx_reserve(c, need))) return rc;
     }
-    return launch_blind_rotate(c, d_lwe_in, d_testv, nullptr, d_out, B, c->ws, s);
+    return launch_blind_rotate(c, d_lwe_in, d_testv, nullptr, d_out, B, c->ws, c->ws_bytes, s);
 }
 
 extern "C" int tfhe_keyswitch_batch(tfhe_ctx* c, const void* d_in, void* d_out, uint32_t B, void* stream) {

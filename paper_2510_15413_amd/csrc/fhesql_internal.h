@@ -177,9 +177,11 @@ size_t word_bytes(const tfhe_ctx* c);
 
 // kernel launchers (each returns a TFHE_* code)
 int launch_bsk_limbs(tfhe_ctx* c, hipStream_t s);
+// ws: blind-rotation workspace of ws_cap bytes (at least blind_rotate_ws_bytes(c, B)
+// under the current tuning, else the launch fails with TFHE_EINVAL).
 int launch_blind_rotate(tfhe_ctx* c, const void* lwe_in, const void* testv_table,
                         const int32_t* tv_index, void* big_out, uint32_t B, void* ws,
-                        hipStream_t s);
+                        size_t ws_cap, hipStream_t s);
 size_t blind_rotate_ws_bytes(const tfhe_ctx* c, uint32_t B);
 int launch_keyswitch(tfhe_ctx* c, const void* big_in, void* out, const uint64_t* out_ptrs,
                      uint32_t B, hipStream_t s);

@@ -701,7 +701,7 @@ struct Exec {
             if (!pc.total) continue;
             if ((rc = launch_combine(c, dsegs + pc.seg_off, dstart + pc.seg_off, pc.nseg, pc.total, lwe, ptrs, tvi, rs))) break;
             if ((rc = launch_blind_rotate(c, lwe, net.lut_table, net.lut_table ? tvi : nullptr, big, pc.total,
-                                          brws, rs)))
+                                          brws, br_b, rs)))
                 break;
             if ((rc = launch_keyswitch(c, big, nullptr, ptrs, pc.total, rs))) break;
         }
@@ -952,6 +952,7 @@ struct sql_server {
     std::unordered_set<uint64_t> done, known;
     void* stage = nullptr;
     uint8_t *lwe = nullptr, *big = nullptr, *brws = nullptr;
+    size_t brws_bytes = 0;
     uint64_t* ptrs = nullptr;
     int32_t* tvi = nullptr;
     Segment* dsegs = nullptr;
@@ -996,6 +997,7 @@ extern "C" int sql_server_create(tfhe_ctx* c, size_t budget, uint32_t max_batch,
     sv->ptrs = (uint64_t*)p; p += ptr_b;
     sv->tvi = (int32_t*)p; p += tvi_b;
     sv->brws = p; p += br_b;
+    sv->brws_bytes = br_b;
     sv->dsegs = (Segment*)p; p += seg_b;
     sv->dstart = (uint32_t*)p;
     sv->in_use = sv->fixed;
@@ -1160,7 +1162,7 @@ extern "C" int sql_server_step(sql_server* sv, void* stream, uint32_t* gates, ui
             (rc = hip_check(c, hipMemcpyAsync(sv->dstart, sv->hstart, nseg * 4, hipMemcpyHostToDevice, s),
                             "server starts")) ||
             (rc = launch_combine(c, sv->dsegs, sv->dstart, (int)nseg, total, sv->lwe, sv->ptrs, sv->tvi, s)) ||
-            (rc = launch_blind_rotate(c, sv->lwe, nullptr, nullptr, sv->big, total, sv->brws, s)) ||
+            (rc = launch_blind_rotate(c, sv->lwe, nullptr, nullptr, sv->big, total, sv->brws, sv->brws_bytes, s)) ||
             (rc = launch_keyswitch(c, sv->big, nullptr, sv->ptrs, total, s)))
             return rc;
     }

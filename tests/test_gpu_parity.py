@@ -467,3 +467,39 @@ def test_server_expression_queries():
     be = C.CipherBackend(p, K)
     sel = [C.select(be, masks[r], list(cts[2][r])) for r in range(rows)]
     assert np.array_equal(alone[0], np.stack(C.sum_tree(be, sel)))
+
+
+@pytest.mark.parametrize("db", [1, 2])
+def test_digit_cache_row_passes_and_server_workspace_check(db):
+    """Several row passes with digits formed per group (the first pass caches
+    each group's digits in global memory, the later passes reload them) give
+    the default bits; a server whose blind-rotation workspace was sized under
+    the default tuning refuses, with an error and without launching, a tick
+    under this tuning, which needs the larger workspace."""
+    p = si.TOY
+    K = keys_for("toy")
+    ctx = ctx_for("toy")
+    rows, w = 19, 4
+    col1, col2, c1, c2 = _table(p, K, rows, w, 60 + db)
+    lit = _lit(p, K, 6, w, 62 + db)
+    srv = fs.Server(ctx, 1 << 34, max_batch=64)
+    outs = []
+    try:
+        for rp, dbk in ((0, 0), (2, db)):
+            ctx.set_tuning(row_pass=rp, digit_blocks=dbk)
+            m, sel = empty(p, rows, p.n + 1), empty(p, rows, w, p.n + 1)
+            ctx.sql_mask_scan(to_dev(p, c1), rows, w, "lt", to_dev(p, lit), m)
+            ctx.sql_masked_select(m, to_dev(p, c2), rows, w, sel)
+            torch.cuda.synchronize()
+            outs.append((from_dev(p, m), from_dev(p, sel)))
+        out = empty(p, fs.sum_width(w, rows), p.n + 1)
+        srv.submit(to_dev(p, c1), to_dev(p, c2), rows, w, "lt", to_dev(p, lit), out)
+        with pytest.raises(fs.FheError, match="workspace"):
+            for _ in range(64):
+                srv.step()
+    finally:
+        ctx.set_tuning(row_pass=0, digit_blocks=0)
+        torch.cuda.synchronize()
+        srv.close()
+    assert np.array_equal(outs[1][0], outs[0][0]) and np.array_equal(outs[1][1], outs[0][1])
+    assert np.array_equal(dec_bits(p, K, outs[0][0]).astype(bool), col1 < 6)
