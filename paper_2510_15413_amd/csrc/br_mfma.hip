@@ -21,7 +21,8 @@
 // fragment is loaded per diagonal and reused by every (a, c) on it.
 // The key limbs of step i are stored (once per context) as reversed extended
 // byte arrays S[x] = limb(Kext[N-1-x]); a lane's 16 A bytes are contiguous
-// in S (unaligned by a per-lane constant, fixed with v_alignbyte).
+// in S (unaligned by a per-lane constant, fixed with v_alignbyte, or for
+// N <= 256 read from one of four byte-shifted copies staged in LDS).
 // Accumulators are laid out [v][N/4][16 cts][4 coefs].  With one row pass
 // every wave keeps its rows in registers across the n steps and stores them
 // at each step's end for the next rotate-diff: component 0 to LDS, component
@@ -35,6 +36,13 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr int CTS = 16;
 constexpr int THREADS = 512;
+// N <= 256: each key slot holds four copies of the key bytes, copy j shifted
+// down by j bytes, so that a lane reads its 16 A bytes as 4 aligned words of
+// copy (b & 3) with no byte alignment on the critical path.  The 4 lanes of a
+// row group that read one word of the single copy now read 4 copies; copy j
+// starts KCOPY_PAD * j bytes further (24 words per copy), which puts the 32
+// lanes of each half-wave on 32 distinct LDS banks.
+constexpr int KCOPY_PAD = 96;
 
 struct BrArgs {
     const void* lwe;          // [B][n+1] words
@@ -148,17 +156,27 @@ struct ARaw {
     uint32_t w[5];
 };
 
-// The 5 dwords covering a lane's 16 A bytes S[b .. b+15] (b unaligned).
+// The 5 dwords covering a lane's 16 A bytes S[b .. b+15] (b unaligned), or
+// with shifted copies (KC = 4) the 4 aligned dwords at b.
+template <int KC>
 FHE_DEV ARaw afrag_raw(const uint8_t* S, int b) {
-    const uint32_t* w = (const uint32_t*)(S + (b & ~3));
+    const uint32_t* w = (const uint32_t*)(S + (KC == 4 ? b : (b & ~3)));
     ARaw r;
 #pragma unroll
-    for (int k = 0; k < 5; k++) r.w[k] = w[k];
+    for (int k = 0; k < (KC == 4 ? 4 : 5); k++) r.w[k] = w[k];
     return r;
 }
 
+template <int KC>
 FHE_DEV v4i afrag_combine(const ARaw& r, int sh) {
     v4i a;
+    if (KC == 4) {
+        a[0] = (int)r.w[0];
+        a[1] = (int)r.w[1];
+        a[2] = (int)r.w[2];
+        a[3] = (int)r.w[3];
+        return a;
+    }
     a[0] = (int)__builtin_amdgcn_alignbyte(r.w[1], r.w[0], sh);
     a[1] = (int)__builtin_amdgcn_alignbyte(r.w[2], r.w[1], sh);
     a[2] = (int)__builtin_amdgcn_alignbyte(r.w[3], r.w[2], sh);
@@ -167,16 +185,20 @@ FHE_DEV v4i afrag_combine(const ARaw& r, int sh) {
 }
 
 // One (u,p) key block for this wave: all limbs, the pass's RP row tiles.
-template <typename T, int R, int RP>
+// KC = 4: the slot holds four copies of the key bytes, copy j shifted down by
+// j bytes, so a lane reads its 16 bytes as 4 aligned words of copy (b & 3).
+template <typename T, int R, int RP, int KC>
 FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr, int pass,
                         T (&delta)[RP][4]) {
     constexpr int N = R * 64;
     constexpr int NL = Torus<T>::LIMBS;
     constexpr int CP = R < 16 ? R : 16;
+    constexpr int KCS = 2 * NL * 2 * N + (KC == 4 ? KCOPY_PAD : 0);  // copy stride
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
-    const int lanebase = (N - 1) - 16 * jr - r + 16 * g;
-    const int sh = lanebase & 3;
+    const int sh0 = ((N - 1) - 16 * jr - r + 16 * g) & 3;
+    const int lanebase = (N - 1) - 16 * jr - r + 16 * g - (KC == 4 ? sh0 : 0);
+    const int sh = KC == 4 ? 0 : sh0;
     for (int cg = 0; cg < R / CP; cg++) {
         v4i bf[CP];
 #pragma unroll
@@ -184,7 +206,7 @@ FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr,
             bf[cc] = *(const v4i*)(dblk + (size_t)(cg * CP + cc) * 1024 + lane * 16);
 #pragma unroll 1
         for (int m = 0; m < NL; m++) {
-            const uint8_t* S = kslot + (size_t)(v * NL + m) * (2 * N);
+            const uint8_t* S = kslot + (KC == 4 ? (size_t)sh0 * KCS : 0) + (size_t)(v * NL + m) * (2 * N);
             v4i acc[RP];
 #pragma unroll
             for (int a = 0; a < RP; a++) acc[a] = v4i{0, 0, 0, 0};
@@ -194,14 +216,14 @@ FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr,
             // The raw LDS loads of iteration s+1 are issued before the MFMAs
             // of iteration s and combined after them.
             const int db = lanebase + 64 * (cg * CP - pass * RP);
-            ARaw r0 = afrag_raw(S, db), r1;
-            v4i A0 = afrag_combine(r0, sh), A1 = A0;
+            ARaw r0 = afrag_raw<KC>(S, db), r1;
+            v4i A0 = afrag_combine<KC>(r0, sh), A1 = A0;
 #pragma unroll
             for (int s = 0; s < CP; s++) {
                 const bool wrap_next = s + 1 >= CP - RP + 1;
                 if (s + 1 < CP) {
-                    r0 = afrag_raw(S, db + 64 * (s + 1));
-                    if (wrap_next) r1 = afrag_raw(S, db + 64 * (s + 1 - CP));
+                    r0 = afrag_raw<KC>(S, db + 64 * (s + 1));
+                    if (wrap_next) r1 = afrag_raw<KC>(S, db + 64 * (s + 1 - CP));
                 }
 #pragma unroll
                 for (int a = 0; a < RP; a++) {
@@ -212,8 +234,8 @@ FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr,
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 if (s + 1 < CP) {
-                    A0 = afrag_combine(r0, sh);
-                    if (wrap_next) A1 = afrag_combine(r1, sh);
+                    A0 = afrag_combine<KC>(r0, sh);
+                    if (wrap_next) A1 = afrag_combine<KC>(r1, sh);
                 }
             }
 #pragma unroll
@@ -236,6 +258,8 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     constexpr int NL = Torus<T>::LIMBS;
     constexpr int KSLOT = 2 * NL * 2 * N;  // bytes of one (u,p) key block
     constexpr int KV = (KSLOT / 16 + THREADS - 1) / THREADS;
+    constexpr int KC = R <= 4 ? 4 : 1;   // shifted key copies per slot
+    constexpr int KCS = KSLOT + (KC == 4 ? KCOPY_PAD : 0);  // copy stride
     constexpr int LG = __builtin_ctz(2 * N);
     constexpr bool ACCL = DG < 0;
     constexpr bool DALL = DG <= 0;   // a step's digits formed before its blocks run
@@ -257,7 +281,7 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     int8_t* dbuf = (int8_t*)smem;
     size_t off = (size_t)(ACCL ? l : DALL ? NB : DG) * R * 1024;
     uint8_t* kbuf = smem + off;
-    off += (size_t)(DOUBLE ? 2 : 1) * KSLOT;
+    off += (size_t)(DOUBLE ? 2 : 1) * KC * KCS;
     T* acc0 = (T*)(smem + off);  // ACCL: accumulator component 0, [N/4][16 cts][4]
 
     // With all digits of a step formed before its blocks (DALL) the
@@ -291,12 +315,14 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     const int v = wave >> 2, jr = wave & 3;
     constexpr int KU = KSLOT / 16;  // uint4 per key block
     uint4 pre[KV];
+    uint32_t pnx[KV];  // KC = 4: the word after each uint4
 #define KEY_LOAD(SRCPTR)                                                   \
     do {                                                                   \
         const uint4* ks_ = (SRCPTR);                                       \
         _Pragma("unroll") for (int q_ = 0; q_ < KV; q_++) {                \
             const int idx_ = tid + q_ * THREADS;                           \
             pre[q_] = (KU % THREADS == 0 || idx_ < KU) ? ks_[idx_ < KU ? idx_ : 0] : make_uint4(0, 0, 0, 0); \
+            if (KC == 4) pnx[q_] = idx_ + 1 < KU ? *(const uint32_t*)(ks_ + idx_ + 1) : 0u; \
         }                                                                  \
     } while (0)
 #define KEY_STORE(DSTPTR)                                                  \
@@ -304,7 +330,18 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
         uint4* kd_ = (uint4*)(DSTPTR);                                     \
         _Pragma("unroll") for (int q_ = 0; q_ < KV; q_++) {                \
             const int idx_ = tid + q_ * THREADS;                           \
-            if (KU % THREADS == 0 || idx_ < KU) kd_[idx_] = pre[q_];       \
+            if (KU % THREADS == 0 || idx_ < KU) {                          \
+                kd_[idx_] = pre[q_];                                       \
+                if (KC == 4) {                                             \
+                    const uint4 w_ = pre[q_];                              \
+                    _Pragma("unroll") for (int j_ = 1; j_ < 4; j_++)       \
+                        kd_[j_ * (KCS / 16) + idx_] = make_uint4(          \
+                            __builtin_amdgcn_alignbyte(w_.y, w_.x, j_),    \
+                            __builtin_amdgcn_alignbyte(w_.z, w_.y, j_),    \
+                            __builtin_amdgcn_alignbyte(w_.w, w_.z, j_),    \
+                            __builtin_amdgcn_alignbyte(pnx[q_], w_.w, j_)); \
+                }                                                          \
+            }                                                              \
         }                                                                  \
     } while (0)
     const uint4* kbase = (const uint4*)a.bsk8;
@@ -388,10 +425,10 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
                 }
                 // (double-buffered: the slot read below was stored before the
                 // previous block's closing barrier)
-                const uint8_t* kslot = kbuf + (DOUBLE ? (size_t)(t & 1) * KSLOT : 0);
+                const uint8_t* kslot = kbuf + (DOUBLE ? (size_t)(t & 1) * KC * KCS : 0);
                 const int8_t* dblk = dbuf + (size_t)(ACCL ? ub % l : DALL ? ub : ub % DG) * R * 1024;
-                mfma_block<T, R, RP>(kslot, dblk, v, jr, pass, delta);
-                if (DOUBLE) KEY_STORE(kbuf + (size_t)((t + 1) & 1) * KSLOT);
+                mfma_block<T, R, RP, KC>(kslot, dblk, v, jr, pass, delta);
+                if (DOUBLE) KEY_STORE(kbuf + (size_t)((t + 1) & 1) * KC * KCS);
                 __syncthreads();
             }
             if (REGACC) {
@@ -467,7 +504,7 @@ int launch_t(tfhe_ctx* c, const BrArgs& a, size_t lds, hipStream_t s) {
 size_t lds_need(const tfhe_ctx* c, int dg) {
     const int N = c->p.N, l = c->p.l;
     const int NL = c->q == 32 ? 4 : 8;
-    const size_t kslot = 2ull * NL * 2 * N;
+    const size_t kslot = N <= 256 ? 4 * (2ull * NL * 2 * N + KCOPY_PAD) : 2ull * NL * 2 * N;
     size_t b = (size_t)(dg < 0 ? l : dg == 0 ? 2 * l : dg) * (N / 64) * 1024;
     b += (dg <= 0 ? 2 : 1) * kslot;
     if (dg < 0) b += (size_t)N * CTS * word_bytes(c);
