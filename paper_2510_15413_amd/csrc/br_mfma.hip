@@ -26,7 +26,8 @@
 // Accumulators are laid out [v][N/4][16 cts][4 coefs].  With one row pass
 // every wave keeps its rows in registers across the n steps and stores them
 // at each step's end for the next rotate-diff: component 0 to LDS, component
-// 1 to a per-workgroup global buffer (L2 resident).  With several passes
+// 1 to LDS too when both fit in 64 KB (small N), else to a per-workgroup
+// global buffer (L2 resident).  With several passes
 // both components live in a global ping-pong buffer.  Digits and key limbs
 // are staged in LDS.
 #include "fhesql_internal.h"
@@ -266,6 +267,8 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     constexpr bool DOUBLE = DALL;
     constexpr int NPASS = R / RP;
     static_assert(!ACCL || NPASS == 1, "LDS accumulator mode needs one row pass");
+    // small N: accumulator component 1 in LDS as well (right after component 0)
+    constexpr bool ACC1L = ACCL && 2 * N * CTS * (int)sizeof(T) <= 65536;
     // Several row passes with digits formed per group: the first pass also
     // writes each group's digits to a per-workgroup global cache (L2
     // resident) and the later passes of the step copy them back to LDS.
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     // accumulator is updated in place; otherwise two buffers alternate.
     T* ws0 = (T*)a.ws + (size_t)blockIdx.x * (DALL ? 1 : 2) * (2 * N * CTS);
     T* ws1 = DALL ? ws0 : ws0 + 2 * N * CTS;
-    T* const acc1 = ws0 + (size_t)N * CTS;  // ACCL: component 1 in global memory
+    T* const acc1 = (ACC1L ? acc0 : ws0) + (size_t)N * CTS;  // ACCL: component 1 (LDS or global)
 
     // this thread's ciphertext in the digit phases and its abar_i, one step ahead
     const int cd = tid & (CTS - 1);
@@ -309,7 +312,7 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
         }
         if (ACCL) acc0[acc_idx<T>(N, 0, j, c)] = 0;
         else ws0[acc_idx<T>(N, 0, j, c)] = 0;
-        ws0[acc_idx<T>(N, 1, j, c)] = body;
+        (ACC1L ? acc0 : ws0)[acc_idx<T>(N, 1, j, c)] = body;
     }
 
     const int v = wave >> 2, jr = wave & 3;
@@ -361,7 +364,7 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     typedef T vec4 __attribute__((ext_vector_type(4)));
     constexpr size_t STEP4 = (size_t)(64 / 4) * CTS * 4;  // 4 row tiles further
     const size_t rbase = acc_idx<T>(N, v, 16 * jr + 4 * (lane >> 4), lane & 15);
-    T* const rowp = (ACCL && v == 0) ? acc0 + rbase : ws0 + rbase;  // this wave's rows
+    T* const rowp = (ACCL && (v == 0 || ACC1L)) ? acc0 + rbase : ws0 + rbase;  // this wave's rows
     T accr[REGACC ? RP : 1][4];
     if (REGACC) {
 #pragma unroll
@@ -484,7 +487,7 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
         T val;
         if (j == 0) val = A0[acc_idx<T>(N, 0, 0, c)];
         else if (j < N) val = (T)(0 - A0[acc_idx<T>(N, 0, N - j, c)]);
-        else val = src[acc_idx<T>(N, 1, 0, c)];
+        else val = (ACC1L ? (const T*)acc0 : (const T*)src)[acc_idx<T>(N, 1, 0, c)];
         out[(size_t)gi * (N + 1) + j] = val;
     }
 }
@@ -507,7 +510,7 @@ size_t lds_need(const tfhe_ctx* c, int dg) {
     const size_t kslot = N <= 256 ? 4 * (2ull * NL * 2 * N + KCOPY_PAD) : 2ull * NL * 2 * N;
     size_t b = (size_t)(dg < 0 ? l : dg == 0 ? 2 * l : dg) * (N / 64) * 1024;
     b += (dg <= 0 ? 2 : 1) * kslot;
-    if (dg < 0) b += (size_t)N * CTS * word_bytes(c);
+    if (dg < 0) b += (size_t)N * CTS * word_bytes(c) * (2ull * N * CTS * word_bytes(c) <= 65536 ? 2 : 1);
     return b;
 }
 
