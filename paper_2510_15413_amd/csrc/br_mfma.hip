@@ -205,10 +205,9 @@ FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr,
 #pragma unroll
         for (int cc = 0; cc < CP; cc++)
             bf[cc] = *(const v4i*)(dblk + (size_t)(cg * CP + cc) * 1024 + lane * 16);
-#pragma unroll 1
-        for (int m = 0; m < NL; m++) {
+        // one limb: its MFMA products for this block in acc[] (int32, exact)
+        auto limb = [&](int m, v4i(&acc)[RP]) {
             const uint8_t* S = kslot + (KC == 4 ? (size_t)sh0 * KCS : 0) + (size_t)(v * NL + m) * (2 * N);
-            v4i acc[RP];
 #pragma unroll
             for (int a = 0; a < RP; a++) acc[a] = v4i{0, 0, 0, 0};
             // Diagonals d = c - a (local) in wrapped pairs: iteration s takes
@@ -239,11 +238,35 @@ FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr,
                     if (wrap_next) A1 = afrag_combine<KC>(r1, sh);
                 }
             }
+        };
+        // limbs whose shifted product has a nonzero low word: full fold
+#pragma unroll 1
+        for (int m = 0; m < (NL < 4 ? NL : 4); m++) {
+            v4i acc[RP];
+            limb(m, acc);
 #pragma unroll
             for (int a = 0; a < RP; a++)
 #pragma unroll
                 for (int e = 0; e < 4; e++)
                     delta[a][e] += (T)((T)(int64_t)acc[a][e] << (8 * m));
+        }
+        if constexpr (NL > 4) {
+            // q = 64, limbs 4..7: the shifted product has a zero low word, so
+            // only the low 32 bits of the limb sum reach the high word
+#pragma unroll 1
+            for (int m = 4; m < NL; m++) {
+                v4i acc[RP];
+                limb(m, acc);
+#pragma unroll
+                for (int a = 0; a < RP; a++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+                        u32x2 w = __builtin_bit_cast(u32x2, delta[a][e]);
+                        w.y += (uint32_t)acc[a][e] << (8 * m - 32);
+                        delta[a][e] = __builtin_bit_cast(T, w);
+                    }
+            }
         }
     }
 }
