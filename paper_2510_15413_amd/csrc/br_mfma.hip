@@ -157,11 +157,11 @@ struct ARaw {
     uint32_t w[5];
 };
 
-// The 5 dwords covering a lane's 16 A bytes S[b .. b+15] (b unaligned), or
-// with shifted copies (KC = 4) the 4 aligned dwords at b.
+// The 5 words at p covering a lane's 16 A bytes (which start sh bytes into
+// the first), or with shifted copies (KC = 4) the 4 words of the fragment.
 template <int KC>
-FHE_DEV ARaw afrag_raw(const uint8_t* S, int b) {
-    const uint32_t* w = (const uint32_t*)(S + (KC == 4 ? b : (b & ~3)));
+FHE_DEV ARaw afrag_raw(const uint8_t* p) {
+    const uint32_t* w = (const uint32_t*)p;
     ARaw r;
 #pragma unroll
     for (int k = 0; k < (KC == 4 ? 4 : 5); k++) r.w[k] = w[k];
@@ -215,15 +215,22 @@ FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr,
             // iteration issues RP independent MFMAs (one per accumulator).
             // The raw LDS loads of iteration s+1 are issued before the MFMAs
             // of iteration s and combined after them.
+            // fragment s of this limb starts at byte db + 64 s, s in (-CP, CP):
+            // rebased so that every word offset is a positive immediate (the
+            // base stays inside LDS: the key slot lies after the digit
+            // buffer, which is longer than 64 CP bytes)
             const int db = lanebase + 64 * (cg * CP - pass * RP);
-            ARaw r0 = afrag_raw<KC>(S, db), r1;
+            int sbo = (db & ~3) - 64 * (CP - 1);
+            __asm__ volatile("" : "+v"(sbo));  // keep the rebased offset as the base
+            const uint8_t* Sb = S + sbo;
+            ARaw r0 = afrag_raw<KC>(Sb + 64 * (CP - 1)), r1;
             v4i A0 = afrag_combine<KC>(r0, sh), A1 = A0;
 #pragma unroll
             for (int s = 0; s < CP; s++) {
                 const bool wrap_next = s + 1 >= CP - RP + 1;
                 if (s + 1 < CP) {
-                    r0 = afrag_raw<KC>(S, db + 64 * (s + 1));
-                    if (wrap_next) r1 = afrag_raw<KC>(S, db + 64 * (s + 1 - CP));
+                    r0 = afrag_raw<KC>(Sb + 64 * (s + CP));
+                    if (wrap_next) r1 = afrag_raw<KC>(Sb + 64 * s);
                 }
 #pragma unroll
                 for (int a = 0; a < RP; a++) {
@@ -387,15 +394,22 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     typedef T vec4 __attribute__((ext_vector_type(4)));
     constexpr size_t STEP4 = (size_t)(64 / 4) * CTS * 4;  // 4 row tiles further
     const size_t rbase = acc_idx<T>(N, v, 16 * jr + 4 * (lane >> 4), lane & 15);
-    T* const rowp = (ACCL && (v == 0 || ACC1L)) ? acc0 + rbase : ws0 + rbase;  // this wave's rows
+    // this wave's rows live in LDS (accumulator components held there) or in
+    // the global buffer; the branch is wave-uniform and keeps each access
+    // in its own address space (a selected pointer would be a flat access)
+    const bool rows_lds = ACCL && (v == 0 || ACC1L);
     T accr[REGACC ? RP : 1][4];
     if (REGACC) {
+        auto get = [&](const T* base) {
 #pragma unroll
-        for (int q = 0; q < (REGACC ? RP : 1); q++) {
-            const vec4 x = *(const vec4*)(rowp + q * STEP4);
+            for (int q = 0; q < (REGACC ? RP : 1); q++) {
+                const vec4 x = *(const vec4*)(base + rbase + q * STEP4);
 #pragma unroll
-            for (int e = 0; e < 4; e++) accr[q][e] = x[e];
-        }
+                for (int e = 0; e < 4; e++) accr[q][e] = x[e];
+            }
+        };
+        if (rows_lds) get(acc0);
+        else get(ws0);
     }
     for (int i = 0; i < n; i++) {
         const int ab = cd_live ? (int)mod_switch<T>(a_next, LG) : 0;
@@ -458,15 +472,21 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
                 __syncthreads();
             }
             if (REGACC) {
-                T* pd = ACCL ? rowp : dst + rbase;
-                __asm__ volatile("" : "+v"(pd));
+                // opaque per step, so the row addresses are formed here
+                // instead of being held across the step loop
+                uint32_t ro = (uint32_t)rbase;
+                __asm__ volatile("" : "+v"(ro));
+                auto put = [&](T* base) {
 #pragma unroll
-                for (int q = 0; q < RP; q++) {
-                    vec4 o;
+                    for (int q = 0; q < RP; q++) {
+                        vec4 o;
 #pragma unroll
-                    for (int e = 0; e < 4; e++) o[e] = delta[q][e];
-                    *(vec4*)(pd + q * STEP4) = o;
-                }
+                        for (int e = 0; e < 4; e++) o[e] = delta[q][e];
+                        *(vec4*)(base + ro + q * STEP4) = o;
+                    }
+                };
+                if (rows_lds) put(acc0);
+                else put(ACCL ? ws0 : dst);
                 continue;
             }
             // dst rows of this pass = src rows + delta (16-byte accesses; all
