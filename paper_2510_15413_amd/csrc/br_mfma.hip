@@ -497,9 +497,10 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
                 constexpr size_t STEP = (size_t)(64 / 4) * CTS * 4;  // 4 row tiles further
                 // opaque per step, so the 2*RP row addresses are formed here
                 // instead of being hoisted out of the step loop
-                const T* ps = src + base0;
-                T* pd = dst + base0;
-                __asm__ volatile("" : "+v"(ps), "+v"(pd));
+                uint32_t bo = (uint32_t)base0;
+                __asm__ volatile("" : "+v"(bo));  // (the offset, so the pointers stay global)
+                const T* ps = src + bo;
+                T* pd = dst + bo;
                 vec4 cur[RP];
 #pragma unroll
                 for (int q = 0; q < RP; q++) cur[q] = *(const vec4*)(ps + q * STEP);
