@@ -100,8 +100,10 @@ int tfhe_set_kernel(tfhe_ctx* ctx, int kind);
  *   TFHE_TUNE_MAX_BATCH  maximum ciphertexts per blind-rotation launch when a
  *                        circuit level is split into launches (default 65536);
  *   TFHE_TUNE_ROW_PASS   MFMA kernel row tiles per pass (0 = default for N,
- *                        otherwise one of the instantiated variants, e.g. N/64
- *                        or N/128 for q = 32).
+ *                        otherwise an instantiated variant -- q = 32: 1 at
+ *                        N = 64, N/64 or N/128 for N = 256..1024, 8 at
+ *                        N = 2048; q = 64: 1 at N = 64, 4 for N = 256..1024,
+ *                        8 or 4 at N = 2048).
  * Returns TFHE_EINVAL for an unknown key or unsupported value. */
 #define TFHE_TUNE_MAX_BATCH 1
 #define TFHE_TUNE_ROW_PASS 2

@@ -627,11 +627,15 @@ size_t dcache_bytes(const tfhe_ctx* c, uint32_t B) {
 bool mfma_row_pass_supported(const tfhe_ctx* c, int rp) {
     const int N = (int)c->p.N;
     if (c->q == 32) {
+        if (N == 64) return rp == 1;
         if (N == 256) return rp == 4 || rp == 2;
         if (N == 512) return rp == 8 || rp == 4;
         if (N == 1024) return rp == 16 || rp == 8;
+        if (N == 2048) return rp == 8;
         return false;
     }
+    if (N == 64) return rp == 1;
+    if (N == 256 || N == 512 || N == 1024) return rp == 4;
     if (N == 2048) return rp == 8 || rp == 4;
     return false;
 }

@@ -503,3 +503,36 @@ def test_digit_cache_row_passes_and_server_workspace_check(db):
         srv.close()
     assert np.array_equal(outs[1][0], outs[0][0]) and np.array_equal(outs[1][1], outs[0][1])
     assert np.array_equal(dec_bits(p, K, outs[0][0]).astype(bool), col1 < 6)
+
+
+# (q, N) pairs the MFMA kernel instantiates beyond the named parameter sets,
+# with their row-pass variants: both accumulator components in LDS (q = 32,
+# N = 512; q = 64, N <= 256), shifted key copies (q = 64, N <= 256), several
+# row passes with the digit cache (q = 64, N = 1024) and the 32-bit 2048 ring
+RINGS = [(32, 512, (8, 4)), (32, 2048, (8,)), (64, 64, (0,)), (64, 256, (0,)), (64, 1024, (0,))]
+
+
+@pytest.mark.parametrize("q,N,passes", RINGS)
+def test_bootstrap_every_ring_size(q, N, passes):
+    """Gate bootstrapping at every other ring size the kernel supports gives
+    the oracle's bits (n = 8 so that the oracle stays fast), for a batch of
+    18 ciphertexts: one full workgroup and a ragged one."""
+    bg, l, ksb, kst, sg = (7, 3, 2, 5, 25) if q == 32 else (6, 4, 3, 6, 51)
+    p = si.Params(f"ring{q}_{N}", q, 8, 1, N, bg, l, ksb, kst, 20, sg)
+    K = oracle.Keys(p, si.KEY_SEED_BASE + 50 + N + q)
+    ctx = context(p, K)
+    B = 18
+    lwe = si.torus(9, N + q, B * (p.n + 1), p.q).reshape(B, p.n + 1)
+    tv = oracle.gate_testv(p)
+    idx = [0, 7, 15, 16, 17]
+    want = oracle.parallel_map(lambda i: oracle.bootstrap(p, K.bsk, lwe[i], tv), idx)
+    for rp in passes:
+        say("ring", q, N, "row pass", rp)
+        ctx.set_tuning(row_pass=rp)
+        out = empty(p, B, p.N + 1)
+        ctx.tfhe_bootstrap_batch(to_dev(p, lwe), out)
+        torch.cuda.synchronize()
+        g = from_dev(p, out)
+        for i, w in zip(idx, want):
+            assert np.array_equal(g[i], w), (q, N, rp, i)
+    ctx.close()
