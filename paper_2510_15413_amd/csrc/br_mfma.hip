@@ -27,9 +27,9 @@
 // every wave keeps its rows in registers across the n steps and stores them
 // at each step's end for the next rotate-diff: component 0 to LDS, component
 // 1 to LDS too when both fit in 64 KB (small N), else to a per-workgroup
-// global buffer (L2 resident).  With several passes
-// both components live in a global ping-pong buffer.  Digits and key limbs
-// are staged in LDS.
+// global buffer (L2 resident).  With several passes both components live in
+// a global ping-pong buffer, and the first pass of a step caches its digits
+// in global memory for the others.  Digits and key limbs are staged in LDS.
 #include "fhesql_internal.h"
 
 namespace {
@@ -214,11 +214,11 @@ FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr,
             // d = s for a <= CP-1-s and d = s - CP for the other a, so every
             // iteration issues RP independent MFMAs (one per accumulator).
             // The raw LDS loads of iteration s+1 are issued before the MFMAs
-            // of iteration s and combined after them.
-            // fragment s of this limb starts at byte db + 64 s, s in (-CP, CP):
-            // rebased so that every word offset is a positive immediate (the
-            // base stays inside LDS: the key slot lies after the digit
-            // buffer, which is longer than 64 CP bytes)
+            // of iteration s and combined after them.  The fragment of
+            // diagonal d starts at byte db + 64 d, d in (-CP, CP); the base is
+            // moved down by 64 (CP-1) bytes so that every word offset is a
+            // positive immediate (it stays inside LDS: the key slot lies
+            // after the digit buffer, which is at least 1 KB per chunk).
             const int db = lanebase + 64 * (cg * CP - pass * RP);
             int sbo = (db & ~3) - 64 * (CP - 1);
             __asm__ volatile("" : "+v"(sbo));  // keep the rebased offset as the base
