@@ -14,7 +14,7 @@ Circuits are written once over a ``backend`` so the same netlist runs on
 plaintext booleans (to pin its logic exhaustively) and on ciphertexts
 (``CipherBackend``, built on the C oracle).
 
-Readings of points the paper leaves open (each listed in the design doc):
+Readings of points the paper leaves open:
 * equality: XNOR per bit, then a balanced AND tree pairing (0,1), (2,3), ...,
   an odd element passing up unchanged;
 * a < c: borrow chain b_j = MAJ(not a_j, c_j, b_{j-1}), b_{-1} = FALSE;
