@@ -8,9 +8,10 @@
 // that picks a table row is then a per-lane value, so the pick is an LDS
 // address rather than a select chain.  For each input coefficient i the
 // t*2^b table rows restricted to the tile's words are staged in LDS (double
-// buffered; each thread loads its share of coefficient i+1 into registers
-// while coefficient i is consumed), and each lane reads the row its digit
-// selects with 16-byte LDS reads.  Rows are padded by 16 bytes so that the
+// buffered; each thread loads its share of the next coefficients into
+// registers while the current ones are consumed; 32-bit words stage up to 8
+// coefficients per barrier), and each lane reads the row its digit selects
+// with 16-byte LDS reads.  Rows are padded by 16 bytes so that the
 // lanes' distinct rows fall on different bank groups.
 #include "fhesql_internal.h"
 
@@ -33,7 +34,7 @@ struct Vec16<uint64_t> {
     static constexpr int N = 2;
 };
 
-template <typename T, int V, int WPW>
+template <typename T, int V, int WPW, int P>
 __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict__ big, const T* __restrict__ ksk,
                                                             T* out, const uint64_t* out_ptrs, int B, int n, int kN,
                                                             int t, int bb) {
@@ -41,8 +42,8 @@ __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict_
     constexpr int EV = Vec16<T>::N;          // words per 16-byte read
     constexpr int RS = WPW + EV;             // LDS row stride in words (16-byte pad)
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    T* tab = (T*)smem;                       // [2][t*V][RS]
-    const int TS = t * V * RS;               // words per buffer
+    T* tab = (T*)smem;                       // [2][P][t*V][RS]
+    const int TS = t * V * RS;               // words per coefficient
     const int tid = threadIdx.x;
     const int c = blockIdx.y * TC + tid;
     const int w0 = blockIdx.x * WPW;
@@ -56,9 +57,25 @@ __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict_
 #pragma unroll
     for (int k = 0; k < WPW; k++) acc[k] = (w0 + k == n && live) ? bigc[kN] : (T)0;
 
-    // this thread's share of the tile rows of coefficient i: element e =
-    // tid + m*THREADS is word e % WPW of row (j, v) = (e / WPW / V, e / WPW % V)
+    // Subtract the rows that coefficient value r selects, from the rows of
+    // one coefficient staged at cbuf.
+    auto consume = [&](const T* cbuf, uint32_t r) {
+        for (int j = 0; j < t; j++) {
+            const uint32_t d = (r >> ((t - 1 - j) * bb)) & (V - 1);
+            const vec* rp = (const vec*)(cbuf + (j * V + d) * RS);
+#pragma unroll
+            for (int q = 0; q < WPW / EV; q++) {
+                const vec x = rp[q];
+#pragma unroll
+                for (int e = 0; e < EV; e++) acc[q * EV + e] -= x[e];
+            }
+        }
+    };
     T pf[PMAX];
+    if constexpr (P == 1) {
+        // One coefficient per barrier: this thread's share of its tile rows,
+        // element e = tid + m*THREADS is word e % WPW of row (j, v) =
+        // (e / WPW / V, e / WPW % V).
 #define KS_FETCH(I)                                                                     \
     do {                                                                                \
         _Pragma("unroll") for (int m = 0; m < PMAX; m++) {                              \
@@ -74,29 +91,59 @@ __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict_
             if (e < E) tab[(size_t)(BUF) * TS + (e / WPW) * RS + e % WPW] = pf[m];      \
         }                                                                               \
     } while (0)
-
-    KS_FETCH(0);
-    KS_STAGE(0);
-    __syncthreads();
-    for (int i = 0; i < kN; i++) {
-        if (i + 1 < kN) KS_FETCH(i + 1);
-        const uint32_t r = live ? (uint32_t)round_top<T>(bigc[i], tb) : 0u;
-        const T* tbuf = tab + (size_t)(i & 1) * TS;
-        for (int j = 0; j < t; j++) {
-            const uint32_t d = (r >> ((t - 1 - j) * bb)) & (V - 1);
-            const vec* rp = (const vec*)(tbuf + (j * V + d) * RS);
-#pragma unroll
-            for (int q = 0; q < WPW / EV; q++) {
-                const vec x = rp[q];
-#pragma unroll
-                for (int e = 0; e < EV; e++) acc[q * EV + e] -= x[e];
-            }
-        }
-        if (i + 1 < kN) KS_STAGE((i + 1) & 1);
+        KS_FETCH(0);
+        KS_STAGE(0);
         __syncthreads();
-    }
+        for (int i = 0; i < kN; i++) {
+            if (i + 1 < kN) KS_FETCH(i + 1);
+            const uint32_t r = live ? (uint32_t)round_top<T>(bigc[i], tb) : 0u;
+            consume(tab + (size_t)(i & 1) * TS, r);
+            if (i + 1 < kN) KS_STAGE((i + 1) & 1);
+            __syncthreads();
+        }
 #undef KS_FETCH
 #undef KS_STAGE
+    } else {
+        // P coefficients per barrier.  Element e = tid + m*THREADS is word
+        // e' % WPW of row (e' / WPW) of coefficient e / E (e' = e % E); its
+        // offsets relative to the group's first coefficient are formed once.
+        int gofs[PMAX], lofs[PMAX];
+#pragma unroll
+        for (int m = 0; m < PMAX; m++) {
+            const int e = tid + m * THREADS;
+            const int ci = e / E, er = e - ci * E;
+            const int k = er % WPW, jv = er / WPW;
+            const bool take = e < P * E;
+            gofs[m] = take && w0 + k <= n ? (ci * t * V + jv) * (int)row + w0 + k : -1;  // -1: stage a zero
+            lofs[m] = take ? ci * TS + jv * RS + k : -1;                                 // -1: nothing to stage
+        }
+        auto fetch = [&](int i0) {
+            const T* kg = ksk + (size_t)i0 * t * V * row;
+#pragma unroll
+            for (int m = 0; m < PMAX; m++) pf[m] = gofs[m] >= 0 ? kg[gofs[m]] : (T)0;
+        };
+        auto stage = [&](int buf) {
+#pragma unroll
+            for (int m = 0; m < PMAX; m++)
+                if (lofs[m] >= 0) tab[(size_t)buf * P * TS + lofs[m]] = pf[m];
+        };
+        fetch(0);
+        stage(0);
+        __syncthreads();
+        for (int i0 = 0, g = 0; i0 < kN; i0 += P, g++) {
+            // this group's coefficients first, so that waiting for them does
+            // not wait for the next group's rows
+            uint32_t rr[P];
+#pragma unroll
+            for (int ii = 0; ii < P; ii++) rr[ii] = live ? (uint32_t)round_top<T>(bigc[i0 + ii], tb) : 0u;
+            if (i0 + P < kN) fetch(i0 + P);
+            const T* tbuf = tab + (size_t)(g & 1) * P * TS;
+#pragma unroll
+            for (int ii = 0; ii < P; ii++) consume(tbuf + ii * TS, rr[ii]);
+            if (i0 + P < kN) stage((g + 1) & 1);
+            __syncthreads();
+        }
+    }
     if (!live) return;
     T* dst = out_ptrs ? (T*)(uintptr_t)out_ptrs[c] : out + (size_t)c * row;
 #pragma unroll
@@ -104,18 +151,33 @@ __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict_
         if (w0 + k <= n) dst[w0 + k] = acc[k];
 }
 
-template <typename T, int V, int WPW>
-int launch_v(tfhe_ctx* c, const T* big, T* out, const uint64_t* out_ptrs, uint32_t B, hipStream_t s) {
+template <typename T, int V, int WPW, int P>
+int launch_p(tfhe_ctx* c, const T* big, T* out, const uint64_t* out_ptrs, uint32_t B, hipStream_t s) {
     const int n = (int)c->p.n, kN = (int)(c->p.k * c->p.N), t = (int)c->p.ks_t, bb = (int)c->p.ks_base_bits;
-    if (t * V * WPW > PMAX * THREADS) return ctx_fail(c, TFHE_EINVAL, "key-switching levels exceed the staging tile");
     constexpr int RS = WPW + Vec16<T>::N;
-    const size_t lds = 2ull * t * V * RS * sizeof(T);
-    auto k = keyswitch_kernel<T, V, WPW>;
+    const size_t lds = 2ull * P * t * V * RS * sizeof(T);
+    auto k = keyswitch_kernel<T, V, WPW, P>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return hip_check(c, e, "hipFuncSetAttribute(keyswitch)");
     dim3 grid((n + 1 + WPW - 1) / WPW, (B + TC - 1) / TC);
     hipLaunchKernelGGL(k, grid, dim3(THREADS), lds, s, big, (const T*)c->d_ksk, out, out_ptrs, (int)B, n, kN, t, bb);
     return hip_check(c, hipGetLastError(), "launch keyswitch");
+}
+
+// Coefficients staged per barrier: with 32-bit words the largest of 8, 4, 2
+// whose rows fit the staging registers and that divides kN (fewer barriers
+// for short LWE tiles); with 64-bit words one, which measured faster.
+template <typename T, int V, int WPW>
+int launch_v(tfhe_ctx* c, const T* big, T* out, const uint64_t* out_ptrs, uint32_t B, hipStream_t s) {
+    const int kN = (int)(c->p.k * c->p.N), t = (int)c->p.ks_t;
+    const int E = t * V * WPW;
+    if (E > PMAX * THREADS) return ctx_fail(c, TFHE_EINVAL, "key-switching levels exceed the staging tile");
+    if constexpr (sizeof(T) == 4) {
+        if (8 * E <= PMAX * THREADS && kN % 8 == 0) return launch_p<T, V, WPW, 8>(c, big, out, out_ptrs, B, s);
+        if (4 * E <= PMAX * THREADS && kN % 4 == 0) return launch_p<T, V, WPW, 4>(c, big, out, out_ptrs, B, s);
+        if (2 * E <= PMAX * THREADS && kN % 2 == 0) return launch_p<T, V, WPW, 2>(c, big, out, out_ptrs, B, s);
+    }
+    return launch_p<T, V, WPW, 1>(c, big, out, out_ptrs, B, s);
 }
 
 // Words per lane: 16, or 8 when the LWE is short (fewer idle lanes in the
