@@ -536,3 +536,25 @@ def test_bootstrap_every_ring_size(q, N, passes):
         for i, w in zip(idx, want):
             assert np.array_equal(g[i], w), (q, N, rp, i)
     ctx.close()
+
+
+@pytest.mark.parametrize("q,ks_bits,ks_t", [(32, 3, 8), (32, 4, 8), (64, 4, 8)])
+def test_keyswitch_staging_variants(q, ks_bits, ks_t):
+    """Key switching with wider key-switching bases, where fewer input
+    coefficients fit one staging round (32-bit: 2 coefficients per barrier at
+    base 2^3 x 8 levels, 1 at base 2^4 x 8), with an LWE of 41 words (a ragged
+    word tile) and 300 ciphertexts (a ragged ciphertext group): the oracle's
+    bits."""
+    p = si.Params(f"ks{q}_{ks_bits}_{ks_t}", q, 40, 1, 256, 8 if q == 32 else 6, 2 if q == 32 else 4,
+                  ks_bits, ks_t, 20, 25 if q == 32 else 51)
+    K = oracle.Keys(p, si.KEY_SEED_BASE + 70 + ks_bits + q)
+    ctx = context(p, K)
+    B = 300
+    big = si.torus(5, 99 + ks_bits, B * (p.k * p.N + 1), p.q).reshape(B, p.k * p.N + 1)
+    out = empty(p, B, p.n + 1)
+    ctx.tfhe_keyswitch_batch(to_dev(p, big), out)
+    torch.cuda.synchronize()
+    g = from_dev(p, out)
+    for i in (0, 1, 127, 255, 256, 299):
+        assert np.array_equal(g[i], oracle.keyswitch(p, K.ksk, big[i])), (q, ks_bits, i)
+    ctx.close()
