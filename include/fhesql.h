@@ -29,8 +29,18 @@
  *  - Pointers named d_* are device pointers (HIP global memory) owned by the
  *    caller; they must stay valid until the stream has finished the call.
  *    Outputs must not alias inputs.  h_* pointers are host memory.
- *  - Calls are asynchronous on the given HIP stream (NULL = default stream)
- *    and are not thread-safe for one context.  Results are a pure function of
+ *  - Calls are stream-ordered on the given HIP stream (NULL = default
+ *    stream): they enqueue their work and return without waiting for the
+ *    device, and their inputs are read and outputs written in stream order.
+ *    The calls of one context share one device workspace; a call on another
+ *    stream than the previous user of the workspace first makes its stream
+ *    wait (hipStreamWaitEvent) for that earlier call, so calls on different
+ *    streams are serialized on the device but never race.  The host blocks
+ *    only when a call must grow the workspace (it then waits for the earlier
+ *    calls that used it), when all pinned staging buffers of level schedules
+ *    are still in flight, in sql_server_step (documented there) and in the
+ *    setup calls (context creation and destruction, tfhe_ctx_sync).  Calls
+ *    are not thread-safe for one context.  Results are a pure function of
  *    the keys and inputs: batching and scheduling never change an output bit.
  *  - Return value: 0 on success, else a negative error code (below);
  *    tfhe_last_error() gives a message.  No C++ exception crosses the ABI.
@@ -84,11 +94,13 @@ typedef struct tfhe_ctx tfhe_ctx;
 size_t tfhe_bsk_words(const tfhe_params* p);
 size_t tfhe_ksk_words(const tfhe_params* p);
 
-/* Create a context: validates p, copies the keys to the device (bsk/ksk are
- * host pointers if keys_on_device == 0, device pointers otherwise; sizes in
- * bytes must match tfhe_bsk_words/tfhe_ksk_words), builds the device-only
- * limb-planar Toeplitz form of the BSK and allocates workspace lazily.
- * The context owns its copies; the caller keeps ownership of bsk/ksk. */
+/* Create a context on the current device: validates p, copies the keys to
+ * the device (bsk/ksk are host pointers if keys_on_device == 0, device
+ * pointers otherwise -- keys generated on the device need no host round trip;
+ * sizes in bytes must match tfhe_bsk_words/tfhe_ksk_words), builds the
+ * device-only limb-planar Toeplitz form of the BSK and allocates workspace
+ * lazily.  Blocks until the keys are on the device.  The context owns its
+ * copies; the caller keeps ownership of bsk/ksk. */
 int tfhe_ctx_create(const tfhe_params* p, const void* bsk, size_t bsk_bytes,
                     const void* ksk, size_t ksk_bytes, int keys_on_device,
                     tfhe_ctx** out);
@@ -178,9 +190,17 @@ typedef struct sql_table_query {
 /* Many tables with uneven row counts and mixed predicates in one level-batched
  * schedule: every level's gates of all tables go into one launch sequence.
  * use_graph != 0 captures the whole schedule into one HIP graph and launches
- * it once. */
+ * it. */
 int sql_scan_batch(tfhe_ctx* ctx, const sql_table_query* q, uint32_t count, int use_graph,
                    void* hip_stream);
+/* With use_graph, the instantiated graph is kept (up to 8 per context, least
+ * recently used evicted) keyed by everything that fixes its launches: the
+ * tables' device addresses and sizes, predicates, the tuning and the
+ * workspace address; repeating a batch relaunches it without a new capture.
+ * A workspace reallocation drops every kept graph.  tfhe_graph_stats reports
+ * the captures and graph launches so far and the graphs kept (any pointer may
+ * be NULL). */
+int tfhe_graph_stats(tfhe_ctx* ctx, uint64_t* captures, uint64_t* launches, uint64_t* cached);
 
 /* ---- Homomorphic expression trees (Section 4.3 B: leaves are operands,
  * inner nodes are operators given as plaintext metadata).

@@ -35,6 +35,7 @@ EXPORTS = [
     "tfhe_set_tuning", "sql_server_create", "sql_server_destroy", "sql_server_submit",
     "sql_server_step", "sql_server_done", "sql_server_bytes_in_use",
     "sql_radix_mask_scan", "sql_radix_masked_select", "sql_radix_sum", "sql_expr_eval", "tfhe_timing_log", "sql_server_submit_expr",
+    "tfhe_graph_stats",
 ]
 # Expression-tree node kinds and comparison operators (sql_expr).
 SQL_EXPR_KINDS = {"column": 0, "const": 1, "literal": 2, "cmp": 3, "and": 4, "or": 5, "xor": 6, "not": 7,
@@ -122,6 +123,7 @@ def load():
         "sql_expr_eval": (i32, [vp, ctypes.POINTER(vp), u32, u32, u32, ctypes.POINTER(SqlExpr), u32, vp, vp]),
         "tfhe_timing_read": (i32, [vp, i32, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(u64)]),
+        "tfhe_graph_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -227,6 +229,13 @@ class Context:
         z = (ctypes.c_uint32 * max(1, n))()
         self._rc(L.tfhe_timing_log(self._h, k, z, n, ctypes.byref(cnt)), "tfhe_timing_log")
         return [("br" if k[i] == 0 else "ks", int(z[i])) for i in range(n)]
+
+    def graph_stats(self):
+        """(captures, graph launches, graphs kept) of sql_scan_batch's graph cache."""
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        self._rc(load().tfhe_graph_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+                 "tfhe_graph_stats")
+        return a.value, b.value, c.value
 
     def set_tuning(self, max_batch=None, row_pass=None, digit_blocks=None):
         L = load()

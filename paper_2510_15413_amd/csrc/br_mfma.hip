@@ -51,7 +51,7 @@ struct BrArgs {
     const void* tv;           // test polynomials [ntv][N] words
     const int32_t* tv_index;  // [B] or null
     void* out;                // [B][N+1] words
-    void* ws;                 // [grid][2][2N*16] words
+    void* ws;                 // accumulator buffers per workgroup (sized by acc_ws_bytes)
     int8_t* dcache;           // [grid][2l][N/64][1024] digit bytes (several row passes) or null
     int B, n, l, bg_bits;
 };
@@ -319,7 +319,11 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
 
     // With all digits of a step formed before its blocks (DALL) the
     // accumulator is updated in place; otherwise two buffers alternate.
-    T* ws0 = (T*)a.ws + (size_t)blockIdx.x * (DALL ? 1 : 2) * (2 * N * CTS);
+    // With component 0 in LDS (ACCL) a workgroup's slot holds component 1
+    // only, and ws0 is placed N*CTS words before it so that component 1
+    // keeps its offset in the [v][N/4][16][4] layout.
+    T* ws0 = ACCL ? (T*)a.ws + ((size_t)blockIdx.x - 1) * (N * CTS)
+                  : (T*)a.ws + (size_t)blockIdx.x * (DALL ? 1 : 2) * (2 * N * CTS);
     T* ws1 = DALL ? ws0 : ws0 + 2 * N * CTS;
     T* const acc1 = (ACC1L ? acc0 : ws0) + (size_t)N * CTS;  // ACCL: component 1 (LDS or global)
 
@@ -607,11 +611,20 @@ int dispatch_dg(tfhe_ctx* c, const BrArgs& a, int dg, hipStream_t s) {
     return ctx_fail(c, TFHE_EINVAL, "parameters exceed LDS capacity of the MFMA kernel");
 }
 
-// Accumulator buffers, then (several row passes with per-group digits) the
-// digit cache.
+// Accumulator buffers per workgroup (words of 2N * CTS per buffer): none
+// when both components stay in LDS, component 1 alone with component 0 in
+// LDS, one buffer updated in place when a step's digits are formed before
+// its blocks, else two alternating buffers.  Then (several row passes with
+// per-group digits) the digit cache.
 size_t acc_ws_bytes(const tfhe_ctx* c, uint32_t B) {
+    const int R = (int)c->p.N / 64, rp = plan_rp(c);
+    if (rp <= 0) return 0;
+    const int dg = plan_dg(c, R, rp);
+    if (dg == kNoFit) return 0;
     const size_t grid = (B + CTS - 1) / CTS;
-    return grid * 2 * 2 * (size_t)c->p.N * CTS * word_bytes(c);
+    const size_t comp = (size_t)c->p.N * CTS * word_bytes(c);  // one component of a workgroup
+    if (dg < 0) return 2 * comp <= 65536 ? 0 : grid * comp;
+    return grid * (dg == 0 ? 1 : 2) * 2 * comp;
 }
 
 size_t dcache_bytes(const tfhe_ctx* c, uint32_t B) {
@@ -650,7 +663,8 @@ int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_
     const int dg = plan_dg(c, N / 64, rp);
     if (dg == kNoFit) return ctx_fail(c, TFHE_EINVAL, "parameters exceed LDS capacity of the MFMA kernel");
     // the tuning may have changed since the workspace was sized
-    if (!ws || mfma_ws_bytes(c, B) > ws_cap)
+    const size_t need = mfma_ws_bytes(c, B);
+    if ((need && !ws) || need > ws_cap)
         return ctx_fail(c, TFHE_EINVAL, "blind-rotation workspace too small for the current tuning");
     BrArgs a;
     a.lwe = lwe_in;

@@ -1,7 +1,9 @@
 // Context management, key preprocessing, device key generation, encryption
 // and the bootstrap / key-switch entry points of the C ABI.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "fhesql_internal.h"
 
@@ -25,14 +27,24 @@ int hip_check(tfhe_ctx* c, hipError_t e, const char* what) {
 
 size_t word_bytes(const tfhe_ctx* c) { return c->q == 32 ? 4 : 8; }
 
-int ctx_reserve(tfhe_ctx* c, size_t bytes) {
-    if (bytes <= c->ws_bytes) return TFHE_OK;
+int ws_acquire(tfhe_ctx* c, hipStream_t s, size_t bytes) {
+    if (bytes <= c->ws_bytes) {
+        if (c->ws_used && c->ws_stream != s)
+            return hip_check(c, hipStreamWaitEvent(s, c->ws_event, 0), "wait for the workspace");
+        return TFHE_OK;
+    }
     if (c->ws) {
-        hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) return hip_check(c, e, "sync before workspace growth");
+        // earlier calls may still read the old buffer, and captured graphs
+        // refer to its address
+        if (c->ws_used) {
+            hipError_t e = hipEventSynchronize(c->ws_event);
+            if (e != hipSuccess) return hip_check(c, e, "wait before workspace growth");
+        }
+        graphs_clear(c);
         hipFree(c->ws);
         c->ws = nullptr;
         c->ws_bytes = 0;
+        c->ws_used = false;
     }
     size_t want = bytes + bytes / 4;
     hipError_t e = hipMalloc(&c->ws, want);
@@ -42,6 +54,63 @@ int ctx_reserve(tfhe_ctx* c, size_t bytes) {
     }
     c->ws_bytes = want;
     return TFHE_OK;
+}
+
+int ws_release(tfhe_ctx* c, hipStream_t s) {
+    if (!c->ws_event) {
+        int rc = hip_check(c, hipEventCreateWithFlags(&c->ws_event, hipEventDisableTiming), "workspace event");
+        if (rc) return rc;
+    }
+    c->ws_stream = s;
+    c->ws_used = true;
+    return hip_check(c, hipEventRecord(c->ws_event, s), "workspace event record");
+}
+
+int stage_upload(tfhe_ctx* c, hipStream_t s, void* d_dst, const void* src, size_t bytes) {
+    if (!bytes) return TFHE_OK;
+    constexpr size_t kMaxStages = 16;
+    // a free buffer: never used or its last copy has completed
+    auto is_free = [](const tfhe_ctx::HostStage& h) { return !h.used || hipEventQuery(h.ev) == hipSuccess; };
+    tfhe_ctx::HostStage* pick = nullptr;
+    for (auto& h : c->stages)
+        if (h.cap >= bytes && is_free(h)) { pick = &h; break; }
+    if (!pick) {
+        tfhe_ctx::HostStage* spare = nullptr;  // a free buffer that is too small
+        for (auto& h : c->stages)
+            if (is_free(h)) { spare = &h; break; }
+        if (!spare && c->stages.size() >= kMaxStages) {
+            // every buffer is in flight: wait for the first one
+            spare = &c->stages[0];
+            int rc = hip_check(c, hipEventSynchronize(spare->ev), "wait for a staging buffer");
+            if (rc) return rc;
+        }
+        if (!spare) {
+            c->stages.push_back(tfhe_ctx::HostStage{nullptr, 0, nullptr, false});
+            spare = &c->stages.back();
+            int rc = hip_check(c, hipEventCreateWithFlags(&spare->ev, hipEventDisableTiming), "staging event");
+            if (rc) { c->stages.pop_back(); return rc; }
+        }
+        if (spare->cap < bytes) {
+            if (spare->p) hipHostFree(spare->p);
+            spare->p = nullptr;
+            spare->cap = 0;
+            const size_t cap = std::max<size_t>(bytes + bytes / 4, 1 << 16);
+            int rc = hip_check(c, hipHostMalloc(&spare->p, cap), "pinned staging buffer");
+            if (rc) return rc;
+            spare->cap = cap;
+        }
+        pick = spare;
+    }
+    memcpy(pick->p, src, bytes);
+    int rc = hip_check(c, hipMemcpyAsync(d_dst, pick->p, bytes, hipMemcpyHostToDevice, s), "upload");
+    if (rc) return rc;
+    pick->used = true;
+    return hip_check(c, hipEventRecord(pick->ev, s), "staging event record");
+}
+
+void graphs_clear(tfhe_ctx* c) {
+    for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
 }
 
 static bool valid_params(const tfhe_params* p, std::string* why) {
@@ -129,6 +198,7 @@ extern "C" int tfhe_ctx_create(const tfhe_params* p, const void* bsk, size_t bsk
     }
     int dev = 0;
     hipGetDevice(&dev);
+    c->device = dev;
     hipGetDeviceProperties(&c->prop, dev);
     const int NL = c->q == 32 ? 4 : 8;
     const size_t polys = (size_t)p->n * (p->k + 1) * p->l * (p->k + 1);
@@ -170,6 +240,12 @@ extern "C" void tfhe_ctx_destroy(tfhe_ctx* c) {
     hipDeviceSynchronize();
     timing_drain(c);
     for (auto e : c->event_pool) hipEventDestroy(e);
+    graphs_clear(c);
+    for (auto& h : c->stages) {
+        if (h.p) hipHostFree(h.p);
+        if (h.ev) hipEventDestroy(h.ev);
+    }
+    if (c->ws_event) hipEventDestroy(c->ws_event);
     if (c->d_bsk) hipFree(c->d_bsk);
     if (c->d_bsk8) hipFree(c->d_bsk8);
     if (c->d_ksk) hipFree(c->d_ksk);
@@ -319,13 +395,20 @@ extern "C" int tfhe_bootstrap_batch(tfhe_ctx* c, const void* d_lwe_in, const voi
     if (!d_lwe_in || !d_out) return ctx_fail(c, TFHE_EINVAL, "null ciphertext pointer");
     hipStream_t s = (hipStream_t)stream;
     const size_t need = blind_rotate_ws_bytes(c, B);
-    if (need) {
-        // the workspace is shared by calls on this context: wait for earlier work
-        int rc = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
-        if (rc) return rc;
-        if ((rc = ctx_reserve(c, need))) return rc;
-    }
-    return launch_blind_rotate(c, d_lwe_in, d_testv, nullptr, d_out, B, c->ws, c->ws_bytes, s);
+    if (!need) return launch_blind_rotate(c, d_lwe_in, d_testv, nullptr, d_out, B, nullptr, 0, s);
+    int rc = ws_acquire(c, s, need);
+    if (rc) return rc;
+    rc = launch_blind_rotate(c, d_lwe_in, d_testv, nullptr, d_out, B, c->ws, c->ws_bytes, s);
+    const int rr = ws_release(c, s);
+    return rc ? rc : rr;
+}
+
+extern "C" int tfhe_graph_stats(tfhe_ctx* c, uint64_t* captures, uint64_t* launches, uint64_t* cached) {
+    if (!c) return TFHE_EINVAL;
+    if (captures) *captures = c->graph_captures;
+    if (launches) *launches = c->graph_launches;
+    if (cached) *cached = c->graphs.size();
+    return TFHE_OK;
 }
 
 extern "C" int tfhe_keyswitch_batch(tfhe_ctx* c, const void* d_in, void* d_out, uint32_t B, void* stream) {

@@ -139,9 +139,35 @@ struct tfhe_ctx {
     void* d_ksk = nullptr;     // [kN][t][2^b][n+1] words
     void* d_gate_tv = nullptr; // N words of 1/8
     void* d_false = nullptr;   // trivial FALSE ciphertext (0^n, -1/8)
-    // workspace pool (grown on demand)
+    // workspace (grown on demand), shared by the calls on this context.  A
+    // call on stream s first makes s wait for the event recorded after the
+    // last call that used it (if that was another stream), so calls stay
+    // stream-ordered without host synchronization.
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    hipEvent_t ws_event = nullptr;
+    hipStream_t ws_stream = nullptr;
+    bool ws_used = false;
+    // pinned host buffers for uploads of level schedules; a buffer is reused
+    // once the copy that last read it has completed
+    struct HostStage {
+        void* p;
+        size_t cap;
+        hipEvent_t ev;
+        bool used;
+    };
+    std::vector<HostStage> stages;
+    // instantiated graphs of level schedules, keyed by everything that
+    // determines their launches (resolved segments, launch sizes, copies,
+    // tuning, workspace address)
+    struct GraphEntry {
+        std::vector<uint8_t> key;
+        hipGraphExec_t exec;
+        uint64_t last_use;
+    };
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_clock = 0, graph_captures = 0, graph_launches = 0;
+    int device = 0;  // the device current at creation, which holds every buffer
     std::string err;
     hipDeviceProp_t prop{};
     // kernel timing (per kind: 0 blind rotation, 1 key switching)
@@ -171,7 +197,16 @@ struct TimedLaunch {
 
 int ctx_fail(tfhe_ctx* c, int code, const std::string& msg);
 int hip_check(tfhe_ctx* c, hipError_t e, const char* what);
-int ctx_reserve(tfhe_ctx* c, size_t bytes);
+// Workspace of at least `bytes` for a call on stream s: grows it if needed
+// (waiting for earlier calls that used the old buffer) and otherwise makes s
+// wait for the last call that used it on another stream.
+int ws_acquire(tfhe_ctx* c, hipStream_t s, size_t bytes);
+// Records that the calls just enqueued on s use the workspace.
+int ws_release(tfhe_ctx* c, hipStream_t s);
+// Enqueues a host-to-device copy of `bytes` from host memory `src` on s
+// through a pinned staging buffer (src may be reused on return).
+int stage_upload(tfhe_ctx* c, hipStream_t s, void* d_dst, const void* src, size_t bytes);
+void graphs_clear(tfhe_ctx* c);
 
 size_t word_bytes(const tfhe_ctx* c);
 

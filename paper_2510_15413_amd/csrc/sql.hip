@@ -653,9 +653,8 @@ struct Exec {
         const size_t seg_b = al(flat.size() * sizeof(Segment));
         const size_t st_b = al(starts.size() * 4);
         const size_t total = tmp_b + lwe_b + big_b + ptr_b + tvi_b + br_b + seg_b + st_b;
-        int rc = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
+        int rc = ws_acquire(c, s, total);
         if (rc) return rc;
-        if ((rc = ctx_reserve(c, total))) return rc;
         uint8_t* base = (uint8_t*)c->ws;
         uint8_t* tmp = base;
         uint8_t* lwe = tmp + tmp_b;
@@ -670,53 +669,102 @@ struct Exec {
             for (int j = 0; j < 3; j++) sg.in[j] = j < sg.nin ? resolve(sg.in[j]) : 0;
             sg.out = resolve(sg.out);
         }
-        if ((rc = hip_check(c, hipMemcpy(dsegs, flat.data(), flat.size() * sizeof(Segment), hipMemcpyHostToDevice), "upload segments")))
-            return rc;
-        if ((rc = hip_check(c, hipMemcpy(dstart, starts.data(), starts.size() * 4, hipMemcpyHostToDevice), "upload starts")))
-            return rc;
-
-        hipStream_t rs = s;
-        hipStream_t cap = nullptr;
-        hipGraph_t graph = nullptr;
-        if (use_graph) {
-            if ((rc = hip_check(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "create capture stream"))) return rc;
-            if ((rc = hip_check(c, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture"))) {
-                hipStreamDestroy(cap);
-                return rc;
-            }
-            rs = cap;
-        }
         for (auto& cp : copies) {
             cp.src = resolve(cp.src);
             cp.dst = resolve(cp.dst);
         }
-        for (auto& pc : pieces) {
-            for (int k = 0; k < pc.ncopy && !rc; k++) {
-                const Copy& cp = copies[pc.copy_off + k];
-                rc = hip_check(c, hipMemcpyAsync((void*)(uintptr_t)cp.dst, (const void*)(uintptr_t)cp.src, cp.bytes,
-                                                 hipMemcpyDeviceToDevice, rs), "level copy");
+        // the segment table and the piece starts, uploaded as one block
+        std::vector<uint8_t> host(seg_b + st_b, 0);
+        memcpy(host.data(), flat.data(), flat.size() * sizeof(Segment));
+        memcpy(host.data() + seg_b, starts.data(), starts.size() * 4);
+        if ((rc = stage_upload(c, s, dsegs, host.data(), host.size()))) return rc;
+
+        auto enqueue = [&](hipStream_t rs) -> int {
+            int e = TFHE_OK;
+            for (auto& pc : pieces) {
+                for (int k = 0; k < pc.ncopy && !e; k++) {
+                    const Copy& cp = copies[pc.copy_off + k];
+                    e = hip_check(c, hipMemcpyAsync((void*)(uintptr_t)cp.dst, (const void*)(uintptr_t)cp.src,
+                                                    cp.bytes, hipMemcpyDeviceToDevice, rs), "level copy");
+                }
+                if (e) break;
+                if (pc.nlin && (e = launch_lin(c, dsegs + pc.lin_off, dstart + pc.lin_off, pc.nlin, pc.lin_total, rs)))
+                    break;
+                if (!pc.total) continue;
+                if ((e = launch_combine(c, dsegs + pc.seg_off, dstart + pc.seg_off, pc.nseg, pc.total, lwe, ptrs, tvi,
+                                        rs)))
+                    break;
+                if ((e = launch_blind_rotate(c, lwe, net.lut_table, net.lut_table ? tvi : nullptr, big, pc.total,
+                                             brws, br_b, rs)))
+                    break;
+                if ((e = launch_keyswitch(c, big, nullptr, ptrs, pc.total, rs))) break;
             }
-            if (rc) break;
-            if (pc.nlin && (rc = launch_lin(c, dsegs + pc.lin_off, dstart + pc.lin_off, pc.nlin, pc.lin_total, rs))) break;
-            if (!pc.total) continue;
-            if ((rc = launch_combine(c, dsegs + pc.seg_off, dstart + pc.seg_off, pc.nseg, pc.total, lwe, ptrs, tvi, rs))) break;
-            if ((rc = launch_blind_rotate(c, lwe, net.lut_table, net.lut_table ? tvi : nullptr, big, pc.total,
-                                          brws, br_b, rs)))
-                break;
-            if ((rc = launch_keyswitch(c, big, nullptr, ptrs, pc.total, rs))) break;
-        }
-        if (use_graph) {
-            hipError_t e = hipStreamEndCapture(cap, &graph);
-            if (!rc) rc = hip_check(c, e, "end capture");
+            return e;
+        };
+        if (!use_graph) {
+            rc = enqueue(s);
+        } else {
+            // A graph is keyed by everything that fixes its launches: the
+            // uploaded table (resolved addresses), the pieces, the copies,
+            // the tuning and the workspace; a schedule seen before relaunches
+            // its instantiated graph.
+            std::vector<uint8_t> key(host);
+            auto put = [&](const void* p, size_t n) {
+                const uint8_t* b = (const uint8_t*)p;
+                key.insert(key.end(), b, b + n);
+            };
+            for (const Piece& pc : pieces) {  // field by field (no padding bytes in the key)
+                const uint64_t f[8] = {pc.seg_off, (uint64_t)pc.nseg, pc.total, pc.copy_off, (uint64_t)pc.ncopy,
+                                       pc.lin_off, (uint64_t)pc.nlin, pc.lin_total};
+                put(f, sizeof f);
+            }
+            put(copies.data(), copies.size() * sizeof(Copy));
+            const uint64_t meta[8] = {(uint64_t)(uintptr_t)net.lut_table, (uint64_t)c->kernel, c->max_batch,
+                                      (uint64_t)c->row_pass, (uint64_t)c->digit_blocks,
+                                      (uint64_t)(uintptr_t)c->ws, (uint64_t)c->ws_bytes, (uint64_t)br_b};
+            put(meta, sizeof meta);
             hipGraphExec_t exec = nullptr;
-            if (!rc) rc = hip_check(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
-            if (!rc) rc = hip_check(c, hipGraphLaunch(exec, s), "graph launch");
-            if (!rc) rc = hip_check(c, hipStreamSynchronize(s), "graph sync");
-            if (exec) hipGraphExecDestroy(exec);
-            if (graph) hipGraphDestroy(graph);
-            hipStreamDestroy(cap);
+            for (auto& g : c->graphs)
+                if (g.key == key) { exec = g.exec; g.last_use = ++c->graph_clock; break; }
+            if (!exec) {
+                hipStream_t cap = nullptr;
+                hipGraph_t graph = nullptr;
+                if ((rc = hip_check(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "create capture stream")))
+                    return rc;
+                rc = hip_check(c, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+                if (!rc) {
+                    rc = enqueue(cap);
+                    hipError_t e = hipStreamEndCapture(cap, &graph);
+                    if (!rc) rc = hip_check(c, e, "end capture");
+                }
+                if (!rc) rc = hip_check(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+                if (graph) hipGraphDestroy(graph);
+                hipStreamDestroy(cap);
+                if (rc) {
+                    ws_release(c, s);
+                    return rc;
+                }
+                constexpr size_t kMaxGraphs = 8;
+                if (c->graphs.size() >= kMaxGraphs) {
+                    // evict the least recently used graph once nothing that
+                    // used the workspace (every graph does) is in flight
+                    auto lru = std::min_element(c->graphs.begin(), c->graphs.end(),
+                                                [](const tfhe_ctx::GraphEntry& a, const tfhe_ctx::GraphEntry& b) {
+                                                    return a.last_use < b.last_use;
+                                                });
+                    if (c->ws_used && (rc = hip_check(c, hipEventSynchronize(c->ws_event), "graph eviction")))
+                        return rc;
+                    hipGraphExecDestroy(lru->exec);
+                    c->graphs.erase(lru);
+                }
+                c->graphs.push_back(tfhe_ctx::GraphEntry{std::move(key), exec, ++c->graph_clock});
+                c->graph_captures++;
+            }
+            rc = hip_check(c, hipGraphLaunch(exec, s), "graph launch");
+            c->graph_launches++;
         }
-        return rc;
+        const int rr = ws_release(c, s);
+        return rc ? rc : rr;
     }
 };
 

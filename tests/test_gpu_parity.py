@@ -10,7 +10,7 @@ import pytest
 import oracle
 import seeded_inputs as si
 from oracle import circuits as C
-from helpers import enc_bits, dec_bits, bits_to_int
+from helpers import enc_bits, dec_bits, bits_to_int, edge_lwe, edge_big
 
 pytestmark = pytest.mark.gpu
 
@@ -538,13 +538,13 @@ def test_bootstrap_every_ring_size(q, N, passes):
     ctx.close()
 
 
-@pytest.mark.parametrize("q,ks_bits,ks_t", [(32, 3, 8), (32, 4, 8), (64, 4, 8)])
+@pytest.mark.parametrize("q,ks_bits,ks_t", [(32, 3, 8), (32, 4, 8), (64, 4, 8), (32, 2, 4), (32, 1, 8)])
 def test_keyswitch_staging_variants(q, ks_bits, ks_t):
-    """Key switching with wider key-switching bases, where fewer input
-    coefficients fit one staging round (32-bit: 2 coefficients per barrier at
-    base 2^3 x 8 levels, 1 at base 2^4 x 8), with an LWE of 41 words (a ragged
-    word tile) and 300 ciphertexts (a ragged ciphertext group): the oracle's
-    bits."""
+    """Key switching with other key-switching bases, where another number of
+    input coefficients fits one staging round (32-bit: 2 coefficients per
+    barrier at base 2^3 x 8 levels, 1 at base 2^4 x 8, 8 at bases 2^2 x 4 and
+    2^1 x 8), with an LWE of 41 words (a ragged word tile) and 300
+    ciphertexts (a ragged ciphertext group): the oracle's bits."""
     p = si.Params(f"ks{q}_{ks_bits}_{ks_t}", q, 40, 1, 256, 8 if q == 32 else 6, 2 if q == 32 else 4,
                   ks_bits, ks_t, 20, 25 if q == 32 else 51)
     K = oracle.Keys(p, si.KEY_SEED_BASE + 70 + ks_bits + q)
@@ -558,3 +558,34 @@ def test_keyswitch_staging_variants(q, ks_bits, ks_t):
     for i in (0, 1, 127, 255, 256, 299):
         assert np.array_equal(g[i], oracle.keyswitch(p, K.ksk, big[i])), (q, ks_bits, i)
     ctx.close()
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_edge_inputs_toy(kernel):
+    """Blind rotation + extraction and key switching on the method's boundary
+    inputs (exact modulus-switch ties, masks switching to 0, N and 2N-1, bbar
+    = 0, the all-zero ciphertext, bodies at exactly +-1/8, key-switch rounding
+    ties and the tie below 2^q): every output word equals the oracle's."""
+    p = si.TOY
+    K = keys_for("toy")
+    ctx = ctx_for("toy")
+    ctx.set_kernel(kernel)
+    lwe = edge_lwe(p, 31)
+    B = len(lwe)
+    out = empty(p, B, p.N + 1)
+    ks = empty(p, B, p.n + 1)
+    ctx.tfhe_bootstrap_batch(to_dev(p, lwe), out)
+    ctx.tfhe_keyswitch_batch(out, ks)
+    big = edge_big(p, 32)
+    ks2 = empty(p, len(big), p.n + 1)
+    ctx.tfhe_keyswitch_batch(to_dev(p, big), ks2)
+    torch.cuda.synchronize()
+    ctx.set_kernel("mfma")
+    g, gk, gk2 = from_dev(p, out), from_dev(p, ks), from_dev(p, ks2)
+    tv = oracle.gate_testv(p)
+    want = oracle.parallel_map(lambda i: oracle.bootstrap(p, K.bsk, lwe[i], tv), range(B))
+    for i in range(B):
+        assert np.array_equal(g[i], want[i]), ("bootstrap", i)
+        assert np.array_equal(gk[i], oracle.keyswitch(p, K.ksk, want[i])), ("keyswitch", i)
+    for i in range(len(big)):
+        assert np.array_equal(gk2[i], oracle.keyswitch(p, K.ksk, big[i])), ("keyswitch edge", i)

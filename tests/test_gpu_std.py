@@ -11,7 +11,7 @@ import pytest
 import oracle
 import seeded_inputs as si
 from oracle import circuits as C
-from helpers import enc_bits, bits_to_int
+from helpers import enc_bits, bits_to_int, edge_lwe, edge_big
 
 pytestmark = pytest.mark.gpu
 
@@ -74,6 +74,33 @@ def test_std_bootstrap_batch_4096(std):
     for i, w_ in zip(idx, want):
         assert np.array_equal(g[i], w_), i
         assert np.array_equal(gk[i], oracle.keyswitch(P, K.ksk, g[i])), i
+
+
+def test_std_edge_inputs(std):
+    """The boundary inputs of the toy edge test at the standard parameters
+    (lg = 11, key-switch rounding to 16 bits): every output word of the
+    bootstrap, of the key switch of its outputs and of the key switch of the
+    crafted big ciphertexts equals the oracle's."""
+    K, ctx = std
+    lwe = edge_lwe(P, 33)
+    B = len(lwe)
+    out = empty(P, B, P.N + 1)
+    ks = empty(P, B, P.n + 1)
+    ctx.tfhe_bootstrap_batch(to_dev(P, lwe), out)
+    ctx.tfhe_keyswitch_batch(out, ks)
+    big = edge_big(P, 34)
+    ks2 = empty(P, len(big), P.n + 1)
+    ctx.tfhe_keyswitch_batch(to_dev(P, big), ks2)
+    torch.cuda.synchronize()
+    g, gk, gk2 = from_dev(P, out), from_dev(P, ks), from_dev(P, ks2)
+    tv = oracle.gate_testv(P)
+    say("oracle bootstraps", B)
+    want = oracle.parallel_map(lambda i: oracle.bootstrap(P, K.bsk, lwe[i], tv), range(B))
+    for i in range(B):
+        assert np.array_equal(g[i], want[i]), ("bootstrap", i)
+        assert np.array_equal(gk[i], oracle.keyswitch(P, K.ksk, want[i])), ("keyswitch", i)
+    for i in range(len(big)):
+        assert np.array_equal(gk2[i], oracle.keyswitch(P, K.ksk, big[i])), ("keyswitch edge", i)
 
 
 def _enc_table(K, rows, w, seed):
