@@ -502,3 +502,77 @@ def radix_sum(be, operands):
             nxt.append(level[-1])
         level = nxt
     return level[0]
+
+
+# ------------------------------------------- level-parallel radix evaluation
+
+class _RLin:
+    __slots__ = ("ins", "weights", "const", "depth")
+
+    def __init__(self, ins, weights, const, depth):
+        self.ins, self.weights, self.const, self.depth = ins, weights, const, depth
+
+
+class _RPbs:
+    __slots__ = ("x", "table", "depth", "val")
+
+    def __init__(self, x, table, depth):
+        self.x, self.table, self.depth, self.val = x, table, depth, None
+
+
+class LazyRadixBackend:
+    """Records a radix circuit (the same lin/pbs calls RadixCipherBackend
+    takes) instead of evaluating it, so that the bootstraps of one depth over
+    many rows run in parallel (``evaluate_radix``).  Leaves are ciphertext
+    arrays.  The results are those of RadixCipherBackend: the same linear
+    combinations and bootstraps, only in another order across independent
+    gates."""
+
+    def __init__(self, p):
+        self.p = p
+        self.nodes = []
+
+    @staticmethod
+    def _depth(x):
+        return x.depth if isinstance(x, (_RLin, _RPbs)) else 0
+
+    def lin(self, ins, weights, const):
+        return _RLin(list(ins), list(weights), const, max(self._depth(x) for x in ins))
+
+    def pbs(self, x, table):
+        nd = _RPbs(x, table, 1 + self._depth(x))
+        self.nodes.append(nd)
+        return nd
+
+
+def _rvalue(cb, x):
+    if isinstance(x, _RPbs):
+        return x.val
+    if isinstance(x, _RLin):
+        return cb.lin([_rvalue(cb, y) for y in x.ins], x.weights, x.const)
+    return np.asarray(x, dtype=np.uint64)
+
+
+def evaluate_radix(p, keys, lazy: LazyRadixBackend, threads=None, progress=None):
+    """Run every recorded programmable bootstrap, depth by depth, on a thread
+    pool; progress(depth_done, depths) is called after each depth."""
+    cb = RadixCipherBackend(p, keys)
+    by_depth = {}
+    for nd in lazy.nodes:
+        by_depth.setdefault(nd.depth, []).append(nd)
+
+    def run(nd):
+        nd.val = cb.pbs(_rvalue(cb, nd.x), nd.table)
+
+    depths = sorted(by_depth)
+    for i, d in enumerate(depths):
+        parallel_map(run, by_depth[d], threads)
+        if progress:
+            progress(i + 1, len(depths))
+
+
+def resolve_radix(p, keys, x):
+    """Ciphertext of a recorded radix value (after evaluate_radix) or leaf."""
+    if isinstance(x, list):
+        return np.stack([resolve_radix(p, keys, v) for v in x])
+    return _rvalue(RadixCipherBackend(p, keys), x)
