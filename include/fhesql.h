@@ -146,6 +146,22 @@ int tfhe_ctx_sync(tfhe_ctx* ctx, void* hip_stream);
 int tfhe_bootstrap_batch(tfhe_ctx* ctx, const void* d_lwe_in, const void* d_testv,
                          void* d_out, uint32_t B, void* hip_stream);
 
+/* tfhe_bootstrap_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments and output bits, but the blind-rotation
+ * workspace is a static device array of tfhe_noalloc_scratch_bytes() bytes
+ * (16 MiB; one copy per device, held until the process ends) and the call
+ * allocates nothing and records no timing events.  A batch whose workspace
+ * would exceed the array fails with TFHE_ESHAPE before any launch (at the
+ * standard 32-bit set up to 4096 ciphertexts fit; parameter sets whose
+ * accumulators stay in LDS need none).  The context's device must be
+ * current.  Every call on a device shares that device's array: calls that
+ * overlap on one GPU (different streams, threads or contexts) race, calls
+ * in one stream are ordered. */
+int tfhe_bootstrap_batch_noalloc(tfhe_ctx* ctx, const void* d_lwe_in, const void* d_testv,
+                                 void* d_out, uint32_t B, void* hip_stream);
+size_t tfhe_noalloc_scratch_bytes(void);
+
 /* LWE key switching of B big ciphertexts d_in [B][kN+1] to d_out [B][n+1]. */
 int tfhe_keyswitch_batch(tfhe_ctx* ctx, const void* d_in, void* d_out, uint32_t B,
                          void* hip_stream);

@@ -35,7 +35,7 @@ EXPORTS = [
     "tfhe_set_tuning", "sql_server_create", "sql_server_destroy", "sql_server_submit",
     "sql_server_step", "sql_server_done", "sql_server_bytes_in_use",
     "sql_radix_mask_scan", "sql_radix_masked_select", "sql_radix_sum", "sql_expr_eval", "tfhe_timing_log", "sql_server_submit_expr",
-    "tfhe_graph_stats",
+    "tfhe_graph_stats", "tfhe_bootstrap_batch_noalloc", "tfhe_noalloc_scratch_bytes",
 ]
 # Expression-tree node kinds and comparison operators (sql_expr).
 SQL_EXPR_KINDS = {"column": 0, "const": 1, "literal": 2, "cmp": 3, "and": 4, "or": 5, "xor": 6, "not": 7,
@@ -124,6 +124,8 @@ def load():
         "tfhe_timing_read": (i32, [vp, i32, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(u64)]),
         "tfhe_graph_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+        "tfhe_bootstrap_batch_noalloc": (i32, [vp, vp, vp, vp, u32, vp]),
+        "tfhe_noalloc_scratch_bytes": (sz, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -259,6 +261,13 @@ class Context:
         B = lwe_in.shape[0] if B is None else B
         self._rc(load().tfhe_bootstrap_batch(self._h, _ptr(lwe_in), _ptr(testv), _ptr(out), B, _stream(stream)),
                  "tfhe_bootstrap_batch")
+
+    def tfhe_bootstrap_batch_noalloc(self, lwe_in, out, testv=None, B=None, stream=None):
+        """tfhe_bootstrap_batch on the library's static scratch array (no allocation)."""
+        _check_dev(lwe_in, "lwe_in"); _check_dev(out, "out"); _check_dev(testv, "testv")
+        B = lwe_in.shape[0] if B is None else B
+        self._rc(load().tfhe_bootstrap_batch_noalloc(self._h, _ptr(lwe_in), _ptr(testv), _ptr(out), B,
+                                                     _stream(stream)), "tfhe_bootstrap_batch_noalloc")
 
     def tfhe_keyswitch_batch(self, big_in, out, B=None, stream=None):
         _check_dev(big_in, "big_in"); _check_dev(out, "out")

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfhesql.so")
-SOURCES = ["ctx.hip", "br_mfma.hip", "br_plain.hip", "keyswitch.hip", "sql.hip"]
+SOURCES = ["ctx.hip", "br_mfma.hip", "br_plain.hip", "keyswitch.hip", "sql.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
