@@ -134,7 +134,18 @@ int tfhe_set_kernel(tfhe_ctx* ctx, int kind);
  * later tuning that needs more makes sql_server_step return TFHE_EINVAL
  * without launching (restore the tuning, or create a new server). */
 #define TFHE_TUNE_DIGIT_BLOCKS 3
+/*   TFHE_TUNE_SPLIT_GROUPS for N >= 256, a blind rotation of at most this
+ *                        many groups of 16 ciphertexts runs each step as two
+ *                        launches that spread every group's digits and
+ *                        output rows over many workgroups (latency of small
+ *                        batches: SUM-tree levels, server ticks) instead of
+ *                        one workgroup per group for all n steps; -1 (the
+ *                        default) = a quarter of the device's CUs for
+ *                        N >= 512 and never for N = 256, 0 = never. */
+#define TFHE_TUNE_SPLIT_GROUPS 4
 int tfhe_set_tuning(tfhe_ctx* ctx, int key, int64_t value);
+/* Current value of a tuning knob (as set, 0 or -1 for the defaults). */
+int tfhe_get_tuning(tfhe_ctx* ctx, int key, int64_t* value);
 
 /* Waits for the stream and reports any asynchronous fault. */
 int tfhe_ctx_sync(tfhe_ctx* ctx, void* hip_stream);

@@ -35,7 +35,7 @@ EXPORTS = [
     "tfhe_set_tuning", "sql_server_create", "sql_server_destroy", "sql_server_submit",
     "sql_server_step", "sql_server_done", "sql_server_bytes_in_use",
     "sql_radix_mask_scan", "sql_radix_masked_select", "sql_radix_sum", "sql_expr_eval", "tfhe_timing_log", "sql_server_submit_expr",
-    "tfhe_graph_stats", "tfhe_bootstrap_batch_noalloc", "tfhe_noalloc_scratch_bytes",
+    "tfhe_graph_stats", "tfhe_bootstrap_batch_noalloc", "tfhe_noalloc_scratch_bytes", "tfhe_get_tuning",
 ]
 # Expression-tree node kinds and comparison operators (sql_expr).
 SQL_EXPR_KINDS = {"column": 0, "const": 1, "literal": 2, "cmp": 3, "and": 4, "or": 5, "xor": 6, "not": 7,
@@ -44,6 +44,7 @@ SQL_CMP_OPS = {"eq": 0, "ne": 1, "lt": 2, "le": 3, "gt": 4, "ge": 5}
 TFHE_TUNE_MAX_BATCH = 1
 TFHE_TUNE_ROW_PASS = 2
 TFHE_TUNE_DIGIT_BLOCKS = 3
+TFHE_TUNE_SPLIT_GROUPS = 4
 
 
 class FheError(RuntimeError):
@@ -126,6 +127,7 @@ def load():
         "tfhe_graph_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)]),
         "tfhe_bootstrap_batch_noalloc": (i32, [vp, vp, vp, vp, u32, vp]),
         "tfhe_noalloc_scratch_bytes": (sz, []),
+        "tfhe_get_tuning": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -239,8 +241,20 @@ class Context:
                  "tfhe_graph_stats")
         return a.value, b.value, c.value
 
-    def set_tuning(self, max_batch=None, row_pass=None, digit_blocks=None):
+    def get_tuning(self):
+        """Current knob values: {max_batch, row_pass, digit_blocks, split_groups}."""
+        out = {}
+        for name, key in (("max_batch", TFHE_TUNE_MAX_BATCH), ("row_pass", TFHE_TUNE_ROW_PASS),
+                          ("digit_blocks", TFHE_TUNE_DIGIT_BLOCKS), ("split_groups", TFHE_TUNE_SPLIT_GROUPS)):
+            v = ctypes.c_int64()
+            self._rc(load().tfhe_get_tuning(self._h, key, ctypes.byref(v)), "tfhe_get_tuning")
+            out[name] = v.value
+        return out
+
+    def set_tuning(self, max_batch=None, row_pass=None, digit_blocks=None, split_groups=None):
         L = load()
+        if split_groups is not None:
+            self._rc(L.tfhe_set_tuning(self._h, TFHE_TUNE_SPLIT_GROUPS, int(split_groups)), "tfhe_set_tuning")
         if digit_blocks is not None:
             self._rc(L.tfhe_set_tuning(self._h, TFHE_TUNE_DIGIT_BLOCKS, int(digit_blocks)), "tfhe_set_tuning")
         if max_batch is not None:

@@ -30,6 +30,8 @@
 // global buffer (L2 resident).  With several passes both components live in
 // a global ping-pong buffer, and the first pass of a step caches its digits
 // in global memory for the others.  Digits and key limbs are staged in LDS.
+#include <algorithm>
+
 #include "fhesql_internal.h"
 
 namespace {
@@ -71,13 +73,18 @@ FHE_DEV size_t acc_idx(int N, int v, int j, int c) {
 // words straddle at most two such groups, so an item takes three vector
 // loads; the loads of G items are issued together.  With GC the packed
 // digits are also written to gdst at the same offsets (the digit cache).
-template <typename T, int R, int U, bool GC = false>
+// With DS > 1 the caller forms slice `ds` of DS equal slices of the items
+// (the multi-workgroup blind rotation spreads one group's digits over DS
+// workgroups).
+template <typename T, int R, int U, bool GC = false, int DS = 1>
 FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u_lo, int p_lo, int p_n, int l,
-                          int bgb, int8_t* gdst = nullptr) {
+                          int bgb, int8_t* gdst = nullptr, int ds = 0) {
     typedef T vec4 __attribute__((ext_vector_type(4)));
     constexpr int N = R * 64;
     constexpr int NG = N / 4;  // 4-word groups per component
-    constexpr int ITEMS = CTS * U * NG;
+    constexpr int ITEMS = CTS * U * NG / DS;
+    static_assert((CTS * U * NG) % (DS * CTS) == 0, "digit slices must hold whole groups of 16 items");
+    const int it0 = ds * ITEMS;
     constexpr int IPT = (ITEMS + THREADS - 1) / THREADS;
     constexpr int G = IPT < 4 ? IPT : 4;
     const int lb = l * bgb;
@@ -98,7 +105,7 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
         for (int k = 0; k < G; k++) {
             const int it = threadIdx.x + (k0 + k) * THREADS;
             if (ITEMS % THREADS != 0 && it >= ITEMS) continue;
-            const int rest = it >> 4;
+            const int rest = (it0 + it) >> 4;
             const int kg = rest & (NG - 1);
             const int u = u_lo + rest / NG;
             const vec4* P = (const vec4*)(src + (size_t)u * NG * CTS * 4) + c;
@@ -112,7 +119,7 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
         for (int k = 0; k < G; k++) {
             const int it = threadIdx.x + (k0 + k) * THREADS;
             if (ITEMS % THREADS != 0 && it >= ITEMS) continue;
-            const int rest = it >> 4;
+            const int rest = (it0 + it) >> 4;
             const int kg = rest & (NG - 1);
             const int u = u_lo + rest / NG;
             // negacyclic sign: a group below zero wraps with a sign flip
@@ -540,6 +547,186 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     }
 }
 
+// ------------------------------------------------ multi-workgroup path
+//
+// A batch of few ciphertexts leaves most CUs idle in the kernel above (one
+// workgroup runs a group of 16 ciphertexts through all n steps).  Here every
+// step is two launches over all groups: split_digits_kernel forms the
+// step's digits of every group into global memory (DS workgroups per group
+// and component), and split_mfma_kernel spreads each group's output rows over
+// R/RP workgroups -- workgroup `pass` computes the row tiles the persistent
+// kernel's row pass `pass` computes, with the same mfma_block -- and writes
+// ACC + delta to the other accumulator buffer.  The arithmetic is the
+// persistent kernel's (integer sums mod 2^q), so the bits are the same.
+
+struct SplitArgs {
+    const void* lwe;          // [B][n+1] words
+    const int8_t* bsk8;       // [n][2l][2][LIMBS][2N]
+    const void* tv;           // test polynomials [ntv][N] words
+    const int32_t* tv_index;  // [B] or null
+    void* out;                // [B][N+1] words
+    void* acc;                // [2][G][2N*16] words (ping-pong)
+    int8_t* dig;              // [G][2l][N/64][1024] digit bytes of the step
+    int B, G, n, l, bg_bits, step;
+};
+
+// Digit slices per group and component: 1024 items (of 4 coefficients) each.
+template <int R>
+constexpr int split_ds() { return R >= 4 ? R / 4 : 1; }
+
+template <typename T, int R>
+__global__ __launch_bounds__(THREADS) void split_init_kernel(SplitArgs a) {
+    constexpr int N = R * 64;
+    constexpr int LG = __builtin_ctz(2 * N);
+    const int g = blockIdx.x;
+    const T* lwe = (const T*)a.lwe;
+    T* acc = (T*)a.acc + (size_t)g * 2 * N * CTS;
+    for (int idx = threadIdx.x; idx < CTS * N; idx += THREADS) {
+        const int c = idx & (CTS - 1), j = idx >> 4;
+        const int gi = g * CTS + c;
+        T body = 0;
+        if (gi < a.B) {
+            const int bb = (int)mod_switch<T>(lwe[(size_t)gi * (a.n + 1) + a.n], LG);
+            const int e = (2 * N - bb) & (2 * N - 1);
+            const T* tv = (const T*)a.tv + (size_t)(a.tv_index ? a.tv_index[gi] : 0) * N;
+            body = monomial_coef<T>([&](int s) -> T { return tv[s]; }, N, e, j);
+        }
+        acc[acc_idx<T>(N, 0, j, c)] = 0;
+        acc[acc_idx<T>(N, 1, j, c)] = body;
+    }
+}
+
+// grid (G, 2 components, DS slices): digits of step a.step for every level.
+template <typename T, int R>
+__global__ __launch_bounds__(THREADS) void split_digits_kernel(SplitArgs a) {
+    constexpr int N = R * 64;
+    constexpr int LG = __builtin_ctz(2 * N);
+    constexpr int DS = split_ds<R>();
+    const int g = blockIdx.x, u = blockIdx.y, ds = blockIdx.z;
+    const int cd = threadIdx.x & (CTS - 1);
+    const int gi = g * CTS + cd;
+    const T* lwe = (const T*)a.lwe;
+    const int ab = gi < a.B ? (int)mod_switch<T>(lwe[(size_t)gi * (a.n + 1) + a.step], LG) : 0;
+    const T* src = (const T*)a.acc + ((size_t)(a.step & 1) * a.G + g) * 2 * N * CTS;
+    int8_t* dst = a.dig + ((size_t)g * 2 * a.l + (size_t)u * a.l) * R * 1024;
+    digits_phase<T, R, 1, false, DS>(src, ab, dst, u, 0, a.l, a.l, a.bg_bits, nullptr, ds);
+}
+
+// grid (G, R/RP): row pass blockIdx.y of group blockIdx.x for step a.step.
+template <typename T, int R, int RP>
+__global__ __launch_bounds__(THREADS, 1) void split_mfma_kernel(SplitArgs a) {
+    constexpr int N = R * 64;
+    constexpr int NL = Torus<T>::LIMBS;
+    constexpr int KSLOT = 2 * NL * 2 * N;  // bytes of one (u,p) key block
+    constexpr int KU = KSLOT / 16;         // uint4 per key block
+    constexpr int KV = (KU + THREADS - 1) / THREADS;
+    constexpr int DU = R * 64;             // uint4 per digit block (R KB)
+    constexpr int DV = (DU + THREADS - 1) / THREADS;
+    const int g = blockIdx.x, pass = blockIdx.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int NB = 2 * a.l;
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    int8_t* dslot = (int8_t*)smem;       // digit block (R KB), then the key block
+    uint8_t* kslot = smem + (size_t)R * 1024;
+    const uint4* kbase = (const uint4*)a.bsk8 + (size_t)a.step * NB * KU;
+    const uint4* dbase = (const uint4*)(a.dig + (size_t)g * NB * R * 1024);
+    uint4 kp[KV], dp[DV];
+    auto load = [&](int ub) {
+#pragma unroll
+        for (int q = 0; q < KV; q++) {
+            const int idx = tid + q * THREADS;
+            if (KU % THREADS == 0 || idx < KU) kp[q] = kbase[(size_t)ub * KU + idx];
+        }
+#pragma unroll
+        for (int q = 0; q < DV; q++) {
+            const int idx = tid + q * THREADS;
+            if (DU % THREADS == 0 || idx < DU) dp[q] = dbase[(size_t)ub * DU + idx];
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < KV; q++) {
+            const int idx = tid + q * THREADS;
+            if (KU % THREADS == 0 || idx < KU) ((uint4*)kslot)[idx] = kp[q];
+        }
+#pragma unroll
+        for (int q = 0; q < DV; q++) {
+            const int idx = tid + q * THREADS;
+            if (DU % THREADS == 0 || idx < DU) ((uint4*)dslot)[idx] = dp[q];
+        }
+    };
+    const int v = wave >> 2, jr = wave & 3;
+    T delta[RP][4];
+#pragma unroll
+    for (int q = 0; q < RP; q++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) delta[q][e] = 0;
+    load(0);
+    for (int ub = 0; ub < NB; ub++) {
+        store();
+        __syncthreads();
+        if (ub + 1 < NB) load(ub + 1);  // in flight during this block's MFMAs
+        mfma_block<T, R, RP, 1>(kslot, dslot, v, jr, pass, delta);
+        __syncthreads();
+    }
+    // rows of this pass: ACC_new = ACC + delta.  Row tile J = jr + 4(pass RP + q)
+    // holds coefficients 16J + 4(lane>>4) + e of ciphertext lane&15.
+    typedef T vec4 __attribute__((ext_vector_type(4)));
+    const T* src = (const T*)a.acc + ((size_t)(a.step & 1) * a.G + g) * 2 * N * CTS;
+    T* dst = (T*)a.acc + ((size_t)((a.step + 1) & 1) * a.G + g) * 2 * N * CTS;
+    const size_t base0 = acc_idx<T>(N, v, 16 * (jr + 4 * pass * RP) + 4 * (lane >> 4), lane & 15);
+    constexpr size_t STEP = (size_t)(64 / 4) * CTS * 4;  // 4 row tiles further
+#pragma unroll
+    for (int q = 0; q < RP; q++) {
+        const vec4 cur = *(const vec4*)(src + base0 + q * STEP);
+        vec4 o;
+#pragma unroll
+        for (int e = 0; e < 4; e++) o[e] = (T)(cur[e] + delta[q][e]);
+        *(vec4*)(dst + base0 + q * STEP) = o;
+    }
+}
+
+// Sample extraction from the final accumulators: a'_0 = A[0], a'_j = -A[N-j], b' = B[0].
+template <typename T, int R>
+__global__ __launch_bounds__(THREADS) void split_extract_kernel(SplitArgs a) {
+    constexpr int N = R * 64;
+    const int g = blockIdx.x;
+    const T* A0 = (const T*)a.acc + ((size_t)(a.n & 1) * a.G + g) * 2 * N * CTS;
+    T* out = (T*)a.out;
+    for (int idx = threadIdx.x; idx < CTS * (N + 1); idx += THREADS) {
+        const int c = idx / (N + 1), j = idx - c * (N + 1);
+        const int gi = g * CTS + c;
+        if (gi >= a.B) continue;
+        T val;
+        if (j == 0) val = A0[acc_idx<T>(N, 0, 0, c)];
+        else if (j < N) val = (T)(0 - A0[acc_idx<T>(N, 0, N - j, c)]);
+        else val = A0[acc_idx<T>(N, 1, 0, c)];
+        out[(size_t)gi * (N + 1) + j] = val;
+    }
+}
+
+template <typename T, int R, int RP>
+int launch_split_t(tfhe_ctx* c, SplitArgs a, hipStream_t s) {
+    constexpr int N = R * 64;
+    constexpr int NL = Torus<T>::LIMBS;
+    // (+16: the last limb's fragments read up to 4 bytes past the key block)
+    const size_t lds = (size_t)R * 1024 + 2ull * NL * 2 * N + 16;
+    auto km = split_mfma_kernel<T, R, RP>;
+    hipError_t e = hipFuncSetAttribute((const void*)km, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return hip_check(c, e, "hipFuncSetAttribute(split_mfma)");
+    auto ki = split_init_kernel<T, R>;
+    auto kd = split_digits_kernel<T, R>;
+    auto kx = split_extract_kernel<T, R>;
+    hipLaunchKernelGGL(ki, dim3(a.G), dim3(THREADS), 0, s, a);
+    for (int i = 0; i < a.n; i++) {
+        a.step = i;
+        hipLaunchKernelGGL(kd, dim3(a.G, 2, split_ds<R>()), dim3(THREADS), 0, s, a);
+        hipLaunchKernelGGL(km, dim3(a.G, R / RP), dim3(THREADS), lds, s, a);
+    }
+    hipLaunchKernelGGL(kx, dim3(a.G), dim3(THREADS), 0, s, a);
+    return hip_check(c, hipGetLastError(), "launch split blind rotation");
+}
+
 template <typename T, int R, int RP, int DG>
 int launch_t(tfhe_ctx* c, const BrArgs& a, size_t lds, hipStream_t s) {
     auto k = br_mfma_kernel<T, R, RP, DG>;
@@ -627,6 +814,35 @@ size_t acc_ws_bytes(const tfhe_ctx* c, uint32_t B) {
     return grid * (dg == 0 ? 1 : 2) * 2 * comp;
 }
 
+// Groups of 16 ciphertexts up to which a batch takes the multi-workgroup
+// path: the split_groups knob, by default a quarter of the CUs for N >= 512
+// (at N = 256 a group's step is too short to gain, so only on request).
+int64_t split_limit(const tfhe_ctx* c) {
+    const int R = (int)c->p.N / 64;
+    if (R < 4) return 0;
+    const int cus = c->prop.multiProcessorCount > 0 ? c->prop.multiProcessorCount : 256;
+    if (c->split_groups >= 0) return c->split_groups;
+    return R >= 8 ? cus / 4 : 0;
+}
+
+// Row tiles per workgroup of the multi-workgroup path for a batch of B (0 =
+// the persistent kernel): one row tile per workgroup while that keeps at
+// most two workgroups per CU, else two.
+int split_rp(const tfhe_ctx* c, uint32_t B) {
+    const int R = (int)c->p.N / 64;
+    if (B == 0) return 0;
+    const int cus = c->prop.multiProcessorCount > 0 ? c->prop.multiProcessorCount : 256;
+    const int64_t lim = split_limit(c);
+    const int64_t G = (B + CTS - 1) / CTS;
+    if (G > lim) return 0;
+    return G * R <= 2 * cus ? 1 : 2;
+}
+
+size_t split_ws_bytes(const tfhe_ctx* c, uint32_t B) {
+    const size_t G = (B + CTS - 1) / CTS;
+    return 2 * G * 2 * (size_t)c->p.N * CTS * word_bytes(c) + G * 2 * (size_t)c->p.l * (c->p.N / 64) * 1024;
+}
+
 size_t dcache_bytes(const tfhe_ctx* c, uint32_t B) {
     const int R = (int)c->p.N / 64, rp = plan_rp(c);
     if (rp <= 0 || R / rp <= 1 || plan_dg(c, R, rp) <= 0) return 0;
@@ -653,7 +869,25 @@ bool mfma_row_pass_supported(const tfhe_ctx* c, int rp) {
     return false;
 }
 
-size_t mfma_ws_bytes(const tfhe_ctx* c, uint32_t B) { return acc_ws_bytes(c, B) + dcache_bytes(c, B); }
+size_t mfma_ws_bytes(const tfhe_ctx* c, uint32_t B) {
+    if (split_rp(c, B)) return split_ws_bytes(c, B);
+    return acc_ws_bytes(c, B) + dcache_bytes(c, B);
+}
+
+// Largest workspace of any batch of at most Bmax ciphertexts (the split
+// path's need grows with B below its threshold, the persistent kernel's
+// with B above it).
+size_t mfma_ws_bytes_upto(const tfhe_ctx* c, uint32_t Bmax) {
+    size_t need = mfma_ws_bytes(c, Bmax);
+    const uint64_t bs = std::min<uint64_t>(Bmax, (uint64_t)split_limit(c) * CTS);
+    if (bs) need = std::max(need, split_ws_bytes(c, (uint32_t)bs));
+    return need;
+}
+
+template <typename T, int R>
+int dispatch_split(tfhe_ctx* c, const SplitArgs& a, int rp, hipStream_t s) {
+    return rp == 1 ? launch_split_t<T, R, 1>(c, a, s) : launch_split_t<T, R, 2>(c, a, s);
+}
 
 int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_t* tv_index,
                    void* big_out, uint32_t B, void* ws, size_t ws_cap, hipStream_t s) {
@@ -666,6 +900,39 @@ int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_
     const size_t need = mfma_ws_bytes(c, B);
     if ((need && !ws) || need > ws_cap)
         return ctx_fail(c, TFHE_EINVAL, "blind-rotation workspace too small for the current tuning");
+    if (const int srp = split_rp(c, B)) {
+        SplitArgs sa;
+        sa.lwe = lwe_in;
+        sa.bsk8 = c->d_bsk8;
+        sa.tv = tv;
+        sa.tv_index = tv_index;
+        sa.out = big_out;
+        sa.acc = ws;
+        const uint32_t G = (B + CTS - 1) / CTS;
+        sa.dig = (int8_t*)ws + 2 * (size_t)G * 2 * N * CTS * word_bytes(c);
+        sa.B = (int)B;
+        sa.G = (int)G;
+        sa.n = (int)c->p.n;
+        sa.l = (int)c->p.l;
+        sa.bg_bits = (int)c->p.bg_bits;
+        sa.step = 0;
+        if (c->q == 32) {
+            switch (N) {
+                case 256: return dispatch_split<uint32_t, 4>(c, sa, srp, s);
+                case 512: return dispatch_split<uint32_t, 8>(c, sa, srp, s);
+                case 1024: return dispatch_split<uint32_t, 16>(c, sa, srp, s);
+                case 2048: return dispatch_split<uint32_t, 32>(c, sa, srp, s);
+            }
+        } else {
+            switch (N) {
+                case 256: return dispatch_split<uint64_t, 4>(c, sa, srp, s);
+                case 512: return dispatch_split<uint64_t, 8>(c, sa, srp, s);
+                case 1024: return dispatch_split<uint64_t, 16>(c, sa, srp, s);
+                case 2048: return dispatch_split<uint64_t, 32>(c, sa, srp, s);
+            }
+        }
+        return ctx_fail(c, TFHE_EINVAL, "unsupported N for the multi-workgroup blind rotation");
+    }
     BrArgs a;
     a.lwe = lwe_in;
     a.bsk8 = c->d_bsk8;

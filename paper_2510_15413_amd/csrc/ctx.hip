@@ -12,6 +12,7 @@ int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_
 int launch_br_plain(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_t* tv_index,
                     void* big_out, uint32_t B, hipStream_t s);
 size_t mfma_ws_bytes(const tfhe_ctx* c, uint32_t B);
+size_t mfma_ws_bytes_upto(const tfhe_ctx* c, uint32_t Bmax);
 static int timing_drain(tfhe_ctx* c);
 
 int ctx_fail(tfhe_ctx* c, int code, const std::string& msg) {
@@ -279,11 +280,27 @@ extern "C" int tfhe_set_tuning(tfhe_ctx* c, int key, int64_t value) {
         c->digit_blocks = (int)value;
         return TFHE_OK;
     }
+    if (key == TFHE_TUNE_SPLIT_GROUPS) {
+        if (value < -1 || value > (1 << 20)) return ctx_fail(c, TFHE_EINVAL, "split groups must be in [-1, 2^20]");
+        c->split_groups = value;
+        return TFHE_OK;
+    }
     if (key == TFHE_TUNE_ROW_PASS) {
         if (value != 0 && !mfma_row_pass_supported(c, (int)value))
             return ctx_fail(c, TFHE_EINVAL, "row tiles per pass not instantiated for this N");
         c->row_pass = (int)value;
         return TFHE_OK;
+    }
+    return ctx_fail(c, TFHE_EINVAL, "unknown tuning key");
+}
+
+extern "C" int tfhe_get_tuning(tfhe_ctx* c, int key, int64_t* value) {
+    if (!c || !value) return TFHE_EINVAL;
+    switch (key) {
+        case TFHE_TUNE_MAX_BATCH: *value = c->max_batch; return TFHE_OK;
+        case TFHE_TUNE_ROW_PASS: *value = c->row_pass; return TFHE_OK;
+        case TFHE_TUNE_DIGIT_BLOCKS: *value = c->digit_blocks; return TFHE_OK;
+        case TFHE_TUNE_SPLIT_GROUPS: *value = c->split_groups; return TFHE_OK;
     }
     return ctx_fail(c, TFHE_EINVAL, "unknown tuning key");
 }
@@ -377,6 +394,10 @@ extern "C" int tfhe_timing_read(tfhe_ctx* c, int kind, uint64_t* launches, doubl
 
 size_t blind_rotate_ws_bytes(const tfhe_ctx* c, uint32_t B) {
     return c->kernel == TFHE_KERNEL_MFMA ? mfma_ws_bytes(c, B) : 0;
+}
+
+size_t blind_rotate_ws_bytes_upto(const tfhe_ctx* c, uint32_t Bmax) {
+    return c->kernel == TFHE_KERNEL_MFMA ? mfma_ws_bytes_upto(c, Bmax) : 0;
 }
 
 int launch_blind_rotate(tfhe_ctx* c, const void* lwe_in, const void* testv_table, const int32_t* tv_index,

@@ -133,6 +133,8 @@ struct tfhe_ctx {
     uint32_t max_batch = 65536;  // ciphertexts per blind-rotation launch in circuits
     int row_pass = 0;            // MFMA row tiles per pass (0 = default)
     int digit_blocks = 0;        // 0 auto, 1 one digit block at a time, 2 pairs of levels
+    int64_t split_groups = -1;   // batches of at most this many 16-ciphertext groups take the
+                                 // multi-workgroup blind rotation (-1 = a quarter of the CUs)
     void* d_radix_tv = nullptr;  // radix look-up test polynomials [8][N] words
     void* d_bsk = nullptr;     // [n][(k+1)l][k+1][N] words
     int8_t* d_bsk8 = nullptr;  // [n][(k+1)l][k+1][LIMBS][2N] Toeplitz limb form
@@ -218,6 +220,8 @@ int launch_blind_rotate(tfhe_ctx* c, const void* lwe_in, const void* testv_table
                         const int32_t* tv_index, void* big_out, uint32_t B, void* ws,
                         size_t ws_cap, hipStream_t s);
 size_t blind_rotate_ws_bytes(const tfhe_ctx* c, uint32_t B);
+// Largest blind-rotation workspace of any batch of at most Bmax ciphertexts.
+size_t blind_rotate_ws_bytes_upto(const tfhe_ctx* c, uint32_t Bmax);
 int launch_keyswitch(tfhe_ctx* c, const void* big_in, void* out, const uint64_t* out_ptrs,
                      uint32_t B, hipStream_t s);
 int launch_combine(tfhe_ctx* c, const Segment* d_segs, const uint32_t* d_seg_start,

@@ -602,7 +602,9 @@ struct Exec {
         const size_t big_b = al((size_t)chunk * bw * wb);
         const size_t ptr_b = al((size_t)chunk * 8);
         const size_t tvi_b = al((size_t)chunk * 4);
-        const size_t br_b = al(blind_rotate_ws_bytes(c, chunk));
+        // pieces of a level can be smaller than the chunk (and then take the
+        // multi-workgroup blind rotation), so size for any batch up to it
+        const size_t br_b = al(blind_rotate_ws_bytes_upto(c, chunk));
         // segments split into chunks: upper bound of pieces
         std::vector<Segment> flat;
         std::vector<uint32_t> starts;
@@ -1024,7 +1026,7 @@ extern "C" int sql_server_create(tfhe_ctx* c, size_t budget, uint32_t max_batch,
                         (size_t)c->p.n * 2 * c->p.l * 2 * NL * 2 * c->p.N;
     const size_t lwe_b = al256((size_t)max_batch * lw * wb), big_b = al256((size_t)max_batch * bw * wb);
     const size_t ptr_b = al256((size_t)max_batch * 8), tvi_b = al256((size_t)max_batch * 4);
-    const size_t br_b = al256(blind_rotate_ws_bytes(c, max_batch));
+    const size_t br_b = al256(blind_rotate_ws_bytes_upto(c, max_batch));
     const size_t seg_b = al256(kSegCap * sizeof(Segment)), st_b = al256(kSegCap * 4);
     const size_t stage_b = lwe_b + big_b + ptr_b + tvi_b + br_b + seg_b + st_b;
     sv->fixed = keys + stage_b;
