@@ -153,3 +153,81 @@ def test_pbs64_full_parameters_sampled():
     assert dec_blocks(p, K, g).tolist() == [x % 16 for x in msgs]
     say("oracle bootstrap, 1 sample")
     assert np.array_equal(g[37], oracle.pbs(p, K.bsk, K.ksk, lwe[37], tv))
+
+
+# --------------------------------------------- full 64-bit parameter set
+
+sys.path.insert(0, __import__("os").path.join(__import__("os").path.dirname(__file__), "golden"))
+import pbs64_case as case  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def pbs64_keys():
+    say("oracle keygen at n=750 N=2048 q=64")
+    return keys("pbs64")
+
+
+def test_pbs64_radix_rows_end_to_end(pbs64_keys):
+    """Config-4 circuits at their own parameters (q=64, n=750, N=2048, l=4,
+    Bg=2^6, key switching 2^3 x 6): the 8-block col1 < c compare, the masked
+    select of col2 and the masked SUM over four rows whose comparisons come
+    out below, equal and above, every output ciphertext word for word against
+    the oracle (stored as SHA-256 prefixes by tests/golden/make_pbs64_golden.py)
+    and decrypted against the integers."""
+    K, ctx = pbs64_keys
+    gold = case.read_golden()
+    p = case.P
+    col1, col2 = case.rows()
+    c = case.literal()
+    A, V = case.encrypt(K, col1, tag_hi=1), case.encrypt(K, col2, tag_hi=2)
+    L = case.encrypt(K, [c], tag_hi=5)[0]
+    rows = len(col1)
+    mask = empty(p, rows, p.n + 1)
+    sel = empty(p, rows, case.NB, p.n + 1)
+    tot = empty(p, case.NB, p.n + 1)
+    say("pbs64 radix compare + select + sum, 4 rows")
+    ctx.sql_radix_mask_scan(to_dev(p, A), rows, case.NB, case.OP, to_dev(p, L), mask)
+    ctx.sql_radix_masked_select(mask, to_dev(p, V), rows, case.NB, sel)
+    ctx.sql_radix_sum(sel, rows, case.NB, tot)
+    torch.cuda.synchronize()
+    gm, gs, gt = from_dev(p, mask), from_dev(p, sel), from_dev(p, tot)
+    truth = [a < c for a in col1]
+    assert truth == [True, False, False, col1[3] < c]
+    for r in range(rows):
+        assert case.digest(gm[r]) == gold[("mask", r)][0], ("mask", r)
+        assert case.decode(K, gm[r]) == (16 if truth[r] else 0)
+        for i in range(case.NB):
+            assert case.digest(gs[r, i]) == gold[("sel", r, i)][0], ("sel", r, i)
+        assert value([case.decode(K, x) for x in gs[r]]) == (col2[r] if truth[r] else 0)
+    for i in range(case.NB):
+        assert case.digest(gt[i]) == gold[("sum", i)][0], ("sum", i)
+    want = sum(v for v, f in zip(col2, truth) if f) % (1 << 32)
+    assert value([case.decode(K, x) for x in gt]) == want
+
+
+def test_pbs64_spot_checks_full_launch(pbs64_keys):
+    """The first compare level of 512 rows (4096 programmable bootstraps with
+    the CMP table, one 4096-ciphertext launch of the persistent kernel, then
+    the key switch): every output decodes to CMP of its block difference,
+    and 32 sampled outputs (including the first and the last) equal the
+    oracle's word for word."""
+    K, ctx = pbs64_keys
+    gold = case.read_golden()
+    p = case.P
+    xs, plain, idx = case.spot_batch(K)
+    B = len(xs)
+    tab = np.array(C.radix_tables()["cmp"], dtype=np.uint64)
+    tv = oracle.lut_testv(p, C.RADIX_P, tab, 1 << (p.q - 6))
+    big = empty(p, B, p.N + 1)
+    out = empty(p, B, p.n + 1)
+    say("pbs64 spot batch", B)
+    ctx.tfhe_bootstrap_batch(to_dev(p, xs), big, testv=to_dev(p, tv))
+    ctx.tfhe_keyswitch_batch(big, out)
+    torch.cuda.synchronize()
+    g = from_dev(p, out)
+    assert len(idx) >= 32
+    for j in idx:
+        assert case.digest(g[j]) == gold[("spot", j)][0], ("spot", j)
+    tabl = C.radix_tables()["cmp"]
+    dec = dec_blocks(p, K, g)
+    assert dec.tolist() == [tabl[x] for x in plain]

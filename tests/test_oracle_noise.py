@@ -26,7 +26,7 @@ def _signed_torus(q, x):
 def test_noise_variances_toy(toy_keys):
     p = si.TOY
     K = toy_keys
-    samples = 1200
+    samples = 2000
     cts = enc_bits(p, K, si.bits(17, 1, samples), 900)
     tv = oracle.gate_testv(p)
     eighth = 1 << (p.q - 3)
