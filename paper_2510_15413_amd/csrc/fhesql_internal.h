@@ -82,47 +82,8 @@ __host__ __device__ __forceinline__ T stream_noise(uint64_t K, uint64_t s, int s
     return (T)(uint64_t)e;
 }
 
-// ------------------------------------------------------------------ gates
-
-// Bootstrapped gates (TFHE gate bootstrapping): constant in units of 1/8 and
-// input weights of the linear combination that precedes the sign bootstrap.
-enum GateOp { G_AND = 0, G_NAND, G_OR, G_NOR, G_XOR, G_XNOR, G_ANDNY, G_MAJ, G_LUT };
-
-struct GateForm {
-    int c8;
-    int nin;
-    int w[3];
-};
-inline GateForm gate_form(int op) {
-    switch (op) {
-        case G_AND: return {-1, 2, {1, 1, 0}};
-        case G_NAND: return {1, 2, {-1, -1, 0}};
-        case G_OR: return {1, 2, {1, 1, 0}};
-        case G_NOR: return {-1, 2, {-1, -1, 0}};
-        case G_XOR: return {2, 2, {2, 2, 0}};
-        case G_XNOR: return {-2, 2, {-2, -2, 0}};
-        case G_ANDNY: return {-1, 2, {-1, 1, 0}};
-        case G_MAJ: return {0, 3, {1, 1, 1}};
-        default: return {0, 0, {0, 0, 0}};
-    }
-}
-
-// One strided group of gates of a level: gate r (0 <= r < rows) combines
-// in[j] + r*in_stride[j] (word addresses) with weights w[j] and a constant,
-// and writes its bootstrapped output to out + r*out_stride.  Constant
-// (trivial) operands are folded into `cst` by the host, so the nin inputs
-// are real ciphertexts.
-struct Segment {
-    uint64_t in[3];
-    int64_t in_stride[3];
-    uint64_t out;
-    int64_t out_stride;
-    uint64_t cst;     // constant body term (torus word)
-    int32_t w[3];
-    int32_t nin;
-    uint32_t rows;
-    int32_t lut;      // test polynomial index, -1 = gate test polynomial
-};
+// Gates, segments and netlists (host-only code shared with the host tests).
+#include "netlist.h"
 
 // ---------------------------------------------------------------- context
 
