@@ -40,23 +40,45 @@ def int8_ops_per_bootstrap(p):
     return 2.0 * (p.k + 1) * p.N * (p.k + 1) * p.l * p.N * limbs * p.n
 
 
-def cpu_baseline(p, threads, per_thread):
+def cpu_model():
+    """CPU model name from /proc/cpuinfo (or the platform string)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(p, threads, per_thread, single=4):
     """Oracle gate bootstraps (blind rotation + extraction + key switch) at the
     workload's parameters on random key material (the work does not depend
-    on the key values), `per_thread` bootstraps on each of `threads` threads."""
+    on the key values): `single` bootstraps on one thread, then `per_thread`
+    bootstraps on each of `threads` threads (the process's CPU share, at most
+    16).  value / cores describe the multi-threaded run."""
     import oracle
     import seeded_inputs as si
     rows = (p.k + 1) * p.l
     bsk = si.torus(5, 3, p.n * rows * (p.k + 1) * p.N, p.q)
     ksk = si.torus(5, 5, p.k * p.N * p.ks_t * (1 << p.ks_bits) * (p.n + 1), p.q)
-    lwe = si.torus(5, 7, threads * per_thread * (p.n + 1), p.q).reshape(-1, p.n + 1)
+    lwe = si.torus(5, 7, max(threads * per_thread, single) * (p.n + 1), p.q).reshape(-1, p.n + 1)
     oracle.lib()
     t0 = time.perf_counter()
-    oracle.parallel_map(lambda i: oracle.gate_bootstrap(p, bsk, ksk, lwe[i]), range(len(lwe)), threads)
+    for i in range(single):
+        oracle.gate_bootstrap(p, bsk, ksk, lwe[i])
+    dt1 = time.perf_counter() - t0
+    cnt = threads * per_thread
+    t0 = time.perf_counter()
+    oracle.parallel_map(lambda i: oracle.gate_bootstrap(p, bsk, ksk, lwe[i]), range(cnt), threads)
     dt = time.perf_counter() - t0
-    return {"value": len(lwe) / dt, "unit": "bootstraps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(lwe)} oracle gate bootstraps (n={p.n}, N={p.N}, l={p.l}) on {threads} threads, "
-                      f"{dt:.1f} s wall"}
+    return {"value": cnt / dt, "unit": "bootstraps/s", "cores": threads, "kind": "oracle",
+            "single_core_value": single / dt1, "nproc": os.cpu_count(),
+            "cpu_share": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(),
+            "sample": f"{single} oracle gate bootstraps (n={p.n}, N={p.N}, l={p.l}) on 1 thread in {dt1:.1f} s, "
+                      f"then {cnt} on {threads} threads in {dt:.1f} s wall"}
 
 
 def code_hash(path):

@@ -346,7 +346,7 @@ typedef struct sql_sum_query {
 } sql_sum_query;
 
 /* hbm_budget_bytes: total device memory the server may account for (keys,
- * staging, temporaries); max_batch: gates per tick. */
+ * two staging sets, temporaries); max_batch: gates per tick. */
 int sql_server_create(tfhe_ctx* ctx, size_t hbm_budget_bytes, uint32_t max_batch,
                       sql_server** out);
 void sql_server_destroy(sql_server* srv);
@@ -362,8 +362,16 @@ int sql_server_submit(sql_server* srv, const sql_sum_query* q, uint64_t* id);
 int sql_server_submit_expr(sql_server* srv, const void* const* d_cols, uint32_t ncols, uint32_t rows,
                            uint32_t w, const sql_expr* nodes, uint32_t nnodes, const void* d_sum_col,
                            void* d_sum, uint64_t* id);
-/* One tick on the stream (blocks until its kernels finish).  Outputs (any may
- * be NULL): gates run, active and queued query counts after the tick. */
+/* Enqueues one tick on the stream and returns while it runs: two ticks may
+ * be in flight (the server alternates two staging sets), so the call blocks
+ * only until the tick before the previous one has finished.  Queries whose
+ * last level ran in a finished tick are retired (sql_server_done turns 1 and
+ * their temporaries go back to the stream-ordered pool), queued queries are
+ * admitted, and the next tick's copies, linear steps and gates are issued.
+ * A tick with nothing to issue waits for the ticks in flight instead, so a
+ * loop that steps until every query is done ends.  Consecutive ticks on
+ * different streams are ordered by an event.  Outputs (any may be NULL):
+ * gates issued, active and queued query counts. */
 int sql_server_step(sql_server* srv, void* hip_stream, uint32_t* gates, uint32_t* active,
                     uint32_t* queued);
 /* 1 when query id has completed (its d_sum holds the result), 0 otherwise,

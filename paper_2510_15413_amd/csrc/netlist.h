@@ -706,6 +706,7 @@ struct ServerQuery {
     size_t seg = 0;     // next segment of that level
     uint32_t row = 0;   // rows of that segment already issued
     bool copies_done = false;
+    uint64_t last_tick = ~0ull;  // the tick that issued its last level
 };
 
 // What one server tick runs: copies, then linear steps, then the gates
@@ -723,7 +724,9 @@ struct Tick {
 // Admission (device memory budget), level-by-level issue of every active
 // query's gates into ticks of at most max_batch gates and seg_cap segments
 // (a level may span ticks; a query's next level is issued only after the
-// tick that issues the last gates of the current one), and retirement.
+// tick that issues the last gates of the current one; ticks run in order on
+// the device, so a tick may be issued before the previous one finished), and
+// retirement once the tick that ran a query's last level has finished.
 struct ServerBook {
     size_t budget = 0;       // device bytes the server may account for
     size_t fixed = 0;        // keys and staging, accounted from creation
@@ -732,6 +735,7 @@ struct ServerBook {
     size_t seg_cap = 1 << 15;
     uint32_t max_active = 256;
     uint64_t next_id = 1;
+    uint64_t ticks = 0;      // ticks issued so far (the next tick's number)
     std::deque<ServerQuery*> queue;
     std::vector<ServerQuery*> active;
     std::unordered_set<uint64_t> done, known;
@@ -783,15 +787,18 @@ struct ServerBook {
         return TFHE_OK;
     }
 
-    // Issues the next tick: every active query in admission order adds its
-    // current level's copies and linear steps (when that level starts) and
-    // as many of its gates as fit.
+    // Issues tick number `ticks`: every active query in admission order adds
+    // its current level's copies and linear steps (when that level starts)
+    // and as many of its gates as fit.
     void next_tick(Tick& t, size_t wb) {
         t = Tick();
         size_t nlin = 0;
         for (auto* q : active) {
+            if (q->level >= q->net.levels.size()) {
+                if (q->last_tick == ~0ull) q->last_tick = ticks;  // (a netlist without levels)
+                continue;
+            }
             if (t.total >= max_batch || t.segs.size() + nlin >= seg_cap) break;
-            if (q->level >= q->net.levels.size()) continue;
             Level& L = q->net.levels[q->level];
             if (!q->copies_done) {
                 if (t.segs.size() + nlin + L.lins.size() >= seg_cap) break;  // the next tick takes this level
@@ -822,17 +829,20 @@ struct ServerBook {
                 q->level++;
                 q->seg = 0;
                 q->copies_done = false;
+                if (q->level >= q->net.levels.size()) q->last_tick = ticks;
             }
         }
+        ticks++;
     }
 
-    // After a tick has completed: retires the queries whose last level it
-    // ran; release(base) frees a query's temporaries.
+    // Retires the queries whose last level ran in a tick before `completed`
+    // (every tick numbered below it has finished on the device);
+    // release(base) frees a query's temporaries.
     template <class Release>
-    void retire(Release release) {
+    void retire(Release release, uint64_t completed) {
         std::vector<ServerQuery*> keep;
         for (auto* q : active) {
-            if (q->level >= q->net.levels.size()) {
+            if (q->level >= q->net.levels.size() && q->last_tick < completed) {
                 done.insert(q->id);
                 release(q->tmp);
                 in_use -= q->tmp_bytes;

@@ -386,21 +386,33 @@ extern "C" int sql_expr_eval(tfhe_ctx* c, const void* const* d_cols, uint32_t nc
 
 // ------------------------------------------------- continuous-batching server
 
-// The server's device side: staging buffers sized for max_batch gates and
-// ServerBook's seg_cap segments, pinned host copies of the segment tables;
-// the bookkeeping (admission, ticks, retirement) is ServerBook's.
-struct sql_server {
-    tfhe_ctx* c = nullptr;
-    ServerBook book;
-    void* stage = nullptr;
+// The server's device side: two staging sets (each sized for max_batch
+// gates and ServerBook's seg_cap segments, with pinned host copies of its
+// segment tables) used by alternate ticks, so that a tick is enqueued while
+// the previous one runs; the bookkeeping (admission, ticks, retirement) is
+// ServerBook's.
+struct ServerStage {
     uint8_t *lwe = nullptr, *big = nullptr, *brws = nullptr;
-    size_t brws_bytes = 0;
     uint64_t* ptrs = nullptr;
     int32_t* tvi = nullptr;
     Segment* dsegs = nullptr;
     uint32_t* dstart = nullptr;
     Segment* hsegs = nullptr;
     uint32_t* hstart = nullptr;
+    hipEvent_t ev = nullptr;   // recorded after the tick that last used this set
+    bool busy = false;
+    uint64_t tick = 0;         // that tick's number
+};
+
+struct sql_server {
+    tfhe_ctx* c = nullptr;
+    ServerBook book;
+    void* stage = nullptr;
+    size_t brws_bytes = 0;
+    ServerStage st[2];
+    uint64_t completed = 0;            // every tick numbered below has finished
+    hipStream_t last_stream = nullptr; // stream of the last tick enqueued
+    int last_set = -1;
 };
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -421,28 +433,33 @@ extern "C" int sql_server_create(tfhe_ctx* c, size_t budget, uint32_t max_batch,
     const size_t ptr_b = al256((size_t)max_batch * 8), tvi_b = al256((size_t)max_batch * 4);
     const size_t br_b = al256(blind_rotate_ws_bytes_upto(c, max_batch));
     const size_t seg_b = al256(cap * sizeof(Segment)), st_b = al256(cap * 4);
-    const size_t stage_b = lwe_b + big_b + ptr_b + tvi_b + br_b + seg_b + st_b;
-    sv->book.fixed = keys + stage_b;
+    const size_t set_b = lwe_b + big_b + ptr_b + tvi_b + br_b + seg_b + st_b;
+    sv->book.fixed = keys + 2 * set_b;
     if (sv->book.fixed > budget) {
         delete sv;
         return ctx_fail(c, TFHE_ENOMEM, "HBM budget smaller than keys + server staging");
     }
-    int rc = hip_check(c, hipMalloc(&sv->stage, stage_b), "server staging");
-    if (!rc) rc = hip_check(c, hipHostMalloc((void**)&sv->hsegs, cap * sizeof(Segment)), "server pinned segments");
-    if (!rc) rc = hip_check(c, hipHostMalloc((void**)&sv->hstart, cap * 4), "server pinned starts");
+    int rc = hip_check(c, hipMalloc(&sv->stage, 2 * set_b), "server staging");
+    for (int k = 0; k < 2 && !rc; k++) {
+        ServerStage& S = sv->st[k];
+        rc = hip_check(c, hipHostMalloc((void**)&S.hsegs, cap * sizeof(Segment)), "server pinned segments");
+        if (!rc) rc = hip_check(c, hipHostMalloc((void**)&S.hstart, cap * 4), "server pinned starts");
+        if (!rc) rc = hip_check(c, hipEventCreateWithFlags(&S.ev, hipEventDisableTiming), "server tick event");
+        if (rc) break;
+        uint8_t* p = (uint8_t*)sv->stage + k * set_b;
+        S.lwe = p; p += lwe_b;
+        S.big = p; p += big_b;
+        S.ptrs = (uint64_t*)p; p += ptr_b;
+        S.tvi = (int32_t*)p; p += tvi_b;
+        S.brws = p; p += br_b;
+        S.dsegs = (Segment*)p; p += seg_b;
+        S.dstart = (uint32_t*)p;
+    }
     if (rc) {
         sql_server_destroy(sv);
         return rc;
     }
-    uint8_t* p = (uint8_t*)sv->stage;
-    sv->lwe = p; p += lwe_b;
-    sv->big = p; p += big_b;
-    sv->ptrs = (uint64_t*)p; p += ptr_b;
-    sv->tvi = (int32_t*)p; p += tvi_b;
-    sv->brws = p; p += br_b;
     sv->brws_bytes = br_b;
-    sv->dsegs = (Segment*)p; p += seg_b;
-    sv->dstart = (uint32_t*)p;
     sv->book.in_use = sv->book.fixed;
     *out = sv;
     return TFHE_OK;
@@ -451,10 +468,14 @@ extern "C" int sql_server_create(tfhe_ctx* c, size_t budget, uint32_t max_batch,
 extern "C" void sql_server_destroy(sql_server* sv) {
     if (!sv) return;
     hipDeviceSynchronize();
-    sv->book.clear([](uint64_t base) { if (base) hipFree((void*)(uintptr_t)base); });
+    sv->book.clear([](uint64_t base) { if (base) hipFreeAsync((void*)(uintptr_t)base, nullptr); });
+    hipDeviceSynchronize();
     if (sv->stage) hipFree(sv->stage);
-    if (sv->hsegs) hipHostFree(sv->hsegs);
-    if (sv->hstart) hipHostFree(sv->hstart);
+    for (auto& S : sv->st) {
+        if (S.hsegs) hipHostFree(S.hsegs);
+        if (S.hstart) hipHostFree(S.hstart);
+        if (S.ev) hipEventDestroy(S.ev);
+    }
     delete sv;
 }
 
@@ -509,60 +530,96 @@ extern "C" int sql_server_submit_expr(sql_server* sv, const void* const* d_cols,
     return server_enqueue(sv, sq, b.wb, id);
 }
 
+// Marks the tick of set k finished once its event has completed (waiting
+// for it when `wait`).
+static int server_poll(sql_server* sv, int k, bool wait) {
+    ServerStage& S = sv->st[k];
+    if (!S.busy) return TFHE_OK;
+    const hipError_t e = wait ? hipEventSynchronize(S.ev) : hipEventQuery(S.ev);
+    if (e == hipErrorNotReady) return TFHE_OK;
+    if (e != hipSuccess) return hip_check(sv->c, e, "server tick");
+    S.busy = false;
+    sv->completed = std::max(sv->completed, S.tick + 1);
+    return TFHE_OK;
+}
+
 extern "C" int sql_server_step(sql_server* sv, void* stream, uint32_t* gates, uint32_t* active, uint32_t* queued) {
     if (!sv) return TFHE_EINVAL;
     tfhe_ctx* c = sv->c;
     hipStream_t s = (hipStream_t)stream;
+    ServerBook& bk = sv->book;
+    // this tick's staging set was last used two ticks ago: wait for that one
+    const int k = (int)(bk.ticks & 1);
+    int rc = server_poll(sv, k, true);
+    if (!rc) rc = server_poll(sv, 1 - k, false);
+    if (rc) return rc;
+    if (!sv->st[0].busy && !sv->st[1].busy) sv->completed = bk.ticks;  // nothing in flight
+    // temporaries go back to the stream-ordered pool after the ticks that used them
+    bk.retire([&](uint64_t base) { hipFreeAsync((void*)(uintptr_t)base, s); }, sv->completed);
     std::string why;
-    int rc = sv->book.admit(
+    rc = bk.admit(
         [&](size_t bytes) -> uint64_t {
             void* p = nullptr;
-            return hipMalloc(&p, bytes) == hipSuccess ? (uint64_t)(uintptr_t)p : 0;
+            return hipMallocAsync(&p, bytes, s) == hipSuccess ? (uint64_t)(uintptr_t)p : 0;
         },
         &why);
     if (rc) return ctx_fail(c, rc, why);
     const size_t wb = word_bytes(c);
     Tick t;
-    sv->book.next_tick(t, wb);
+    const uint64_t tick_no = bk.ticks;
+    bk.next_tick(t, wb);
     const size_t nseg = t.segs.size();
-    for (auto& cp : t.copies) {
-        rc = hip_check(c, hipMemcpyAsync((void*)(uintptr_t)cp.dst, (const void*)(uintptr_t)cp.src, cp.bytes,
-                                         hipMemcpyDeviceToDevice, s), "server copy");
-        if (rc) return rc;
-    }
-    // gate segments first, then the linear steps, in the staging arrays
-    for (size_t k = 0; k < nseg; k++) {
-        sv->hsegs[k] = t.segs[k];
-        sv->hstart[k] = t.starts[k];
-    }
-    for (size_t k = 0; k < t.lins.size(); k++) {
-        sv->hsegs[nseg + k] = t.lins[k];
-        sv->hstart[nseg + k] = t.lin_starts[k];
-    }
-    if (!t.lins.empty()) {
-        const size_t nl = t.lins.size();
-        if ((rc = hip_check(c, hipMemcpyAsync(sv->dsegs + nseg, sv->hsegs + nseg, nl * sizeof(Segment),
-                                              hipMemcpyHostToDevice, s), "server linear steps")) ||
-            (rc = hip_check(c, hipMemcpyAsync(sv->dstart + nseg, sv->hstart + nseg, nl * 4, hipMemcpyHostToDevice, s),
-                            "server linear starts")) ||
-            (rc = launch_lin(c, sv->dsegs + nseg, sv->dstart + nseg, (int)nl, t.lin_total, s)))
+    const bool work = t.total || !t.lins.empty() || !t.copies.empty();
+    if (work) {
+        ServerStage& S = sv->st[k];
+        // a tick reads the outputs of the previous one: order the streams
+        if (sv->last_set >= 0 && sv->last_stream != s && sv->st[sv->last_set].busy &&
+            (rc = hip_check(c, hipStreamWaitEvent(s, sv->st[sv->last_set].ev, 0), "server tick order")))
             return rc;
-    }
-    if (t.total) {
-        if ((rc = hip_check(c, hipMemcpyAsync(sv->dsegs, sv->hsegs, nseg * sizeof(Segment), hipMemcpyHostToDevice, s),
+        for (auto& cp : t.copies) {
+            rc = hip_check(c, hipMemcpyAsync((void*)(uintptr_t)cp.dst, (const void*)(uintptr_t)cp.src, cp.bytes,
+                                             hipMemcpyDeviceToDevice, s), "server copy");
+            if (rc) return rc;
+        }
+        // gate segments first, then the linear steps, in the staging arrays
+        for (size_t i = 0; i < nseg; i++) {
+            S.hsegs[i] = t.segs[i];
+            S.hstart[i] = t.starts[i];
+        }
+        for (size_t i = 0; i < t.lins.size(); i++) {
+            S.hsegs[nseg + i] = t.lins[i];
+            S.hstart[nseg + i] = t.lin_starts[i];
+        }
+        const size_t nall = nseg + t.lins.size();
+        if ((rc = hip_check(c, hipMemcpyAsync(S.dsegs, S.hsegs, nall * sizeof(Segment), hipMemcpyHostToDevice, s),
                             "server segments")) ||
-            (rc = hip_check(c, hipMemcpyAsync(sv->dstart, sv->hstart, nseg * 4, hipMemcpyHostToDevice, s),
-                            "server starts")) ||
-            (rc = launch_combine(c, sv->dsegs, sv->dstart, (int)nseg, t.total, sv->lwe, sv->ptrs, sv->tvi, s)) ||
-            (rc = launch_blind_rotate(c, sv->lwe, nullptr, nullptr, sv->big, t.total, sv->brws, sv->brws_bytes, s)) ||
-            (rc = launch_keyswitch(c, sv->big, nullptr, sv->ptrs, t.total, s)))
+            (rc = hip_check(c, hipMemcpyAsync(S.dstart, S.hstart, nall * 4, hipMemcpyHostToDevice, s),
+                            "server starts")))
             return rc;
+        if (!t.lins.empty() &&
+            (rc = launch_lin(c, S.dsegs + nseg, S.dstart + nseg, (int)t.lins.size(), t.lin_total, s)))
+            return rc;
+        if (t.total) {
+            if ((rc = launch_combine(c, S.dsegs, S.dstart, (int)nseg, t.total, S.lwe, S.ptrs, S.tvi, s)) ||
+                (rc = launch_blind_rotate(c, S.lwe, nullptr, nullptr, S.big, t.total, S.brws, sv->brws_bytes, s)) ||
+                (rc = launch_keyswitch(c, S.big, nullptr, S.ptrs, t.total, s)))
+                return rc;
+        }
+        if ((rc = hip_check(c, hipEventRecord(S.ev, s), "server tick event"))) return rc;
+        S.busy = true;
+        S.tick = tick_no;
+        sv->last_stream = s;
+        sv->last_set = k;
+    } else {
+        // nothing to issue: let the ticks in flight finish so that finished
+        // queries retire and the caller's loop makes progress
+        if ((rc = server_poll(sv, 0, true)) || (rc = server_poll(sv, 1, true))) return rc;
+        sv->completed = bk.ticks;
+        bk.retire([&](uint64_t base) { hipFreeAsync((void*)(uintptr_t)base, s); }, sv->completed);
     }
-    if ((rc = hip_check(c, hipStreamSynchronize(s), "server tick"))) return rc;
-    sv->book.retire([](uint64_t base) { hipFree((void*)(uintptr_t)base); });
     if (gates) *gates = t.total;
-    if (active) *active = (uint32_t)sv->book.active.size();
-    if (queued) *queued = (uint32_t)sv->book.queue.size();
+    if (active) *active = (uint32_t)bk.active.size();
+    if (queued) *queued = (uint32_t)bk.queue.size();
     return TFHE_OK;
 }
 

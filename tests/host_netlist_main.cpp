@@ -402,6 +402,7 @@ static void test_server(std::mt19937_64& rng) {
     const int q = 32;
     const uint32_t n = 5, w = 4;
     for (uint32_t mb : {16u, 50u, 4096u}) {
+      for (uint64_t lag : {0ull, 1ull}) {
         Machine m(q, n);
         ServerBook book;
         book.max_batch = mb;
@@ -477,14 +478,22 @@ static void test_server(std::mt19937_64& rng) {
             for (auto& cp : t.copies) m.copy(cp);
             m.lins(t.lins.data(), t.lins.size());
             m.gates(t.segs.data(), t.segs.size());
-            book.retire([&](uint64_t base) { CHECK(allocs.erase(base) == 1, "release of an unknown base"); });
+            // the device finishes ticks in order; with `lag` ticks in flight
+            // only the ticks before the last `lag` have completed
+            const uint64_t completed = book.ticks > lag ? book.ticks - lag : 0;
+            for (auto* q : book.active)
+                CHECK(!(q->level >= q->net.levels.size() && q->last_tick >= book.ticks), "last tick not recorded");
+            book.retire([&](uint64_t base) { CHECK(allocs.erase(base) == 1, "release of an unknown base"); },
+                        completed);
         }
+        book.retire([&](uint64_t base) { CHECK(allocs.erase(base) == 1, "release of an unknown base"); }, book.ticks);
         CHECK(book.in_use == book.fixed, "in use %zu after the last query, fixed %zu", book.in_use, book.fixed);
         CHECK(allocs.empty(), "temporaries not released");
         for (auto& x : qs) {
             CHECK(book.done.count(x.id) == 1, "query %llu not done", (unsigned long long)x.id);
             CHECK(read_bits(m, x.sum, x.width) == x.want, "server sum (batch %u)", mb);
         }
+      }
     }
 }
 

@@ -11,7 +11,7 @@ import pytest
 import oracle
 import seeded_inputs as si
 from oracle import circuits as C
-from helpers import enc_bits, bits_to_int, edge_lwe, edge_big
+from helpers import enc_bits, dec_bits, bits_to_int, edge_lwe, edge_big
 
 pytestmark = pytest.mark.gpu
 
@@ -184,3 +184,39 @@ def test_std_scan_64_row_sample(std, scan4096, part):
         assert np.array_equal(sc["m_eq"][r], C.resolve(P, m)), r
         assert np.array_equal(sc["s_eq"][r], C.resolve(P, sel)), r
         assert np.array_equal(sc["m_lt"][r], C.resolve(P, lt)), r
+
+
+def test_std_server_small_queries(std):
+    """Two small SUM queries served together at the standard parameters (the
+    narrow levels take the multi-workgroup blind rotation): the oracle's
+    bits, and the decrypted sums."""
+    K, ctx = std
+    w = 4
+    col1, col2, c1, c2 = _enc_table(K, 6, w, 77)
+    specs = [(6, "eq", int(col1[2])), (3, "lt", 9)]
+    lits = [enc_bits(P, K, [(c >> j) & 1 for j in range(w)], 780 + k) for k, (_, _, c) in enumerate(specs)]
+    srv = fs.Server(ctx, 1 << 34, max_batch=256)
+    d1, d2 = to_dev(P, c1), to_dev(P, c2)
+    outs, ids = [], []
+    for k, (rows, op, _) in enumerate(specs):
+        outs.append(empty(P, fs.sum_width(w, rows), P.n + 1))
+        ids.append(srv.submit(d1[:rows], d2[:rows], rows, w, op, to_dev(P, lits[k]), outs[k]))
+    ticks = 0
+    while not all(srv.done(i) for i in ids):
+        srv.step()
+        ticks += 1
+        assert ticks < 1000
+    srv.close()
+    say("std server done in", ticks, "ticks")
+    lz = C.LazyBackend(P)
+    roots = []
+    for k, (rows, op, _) in enumerate(specs):
+        sel = [C.select(lz, C.predicate(lz, op, list(c1[r]), list(lits[k])), list(c2[r])) for r in range(rows)]
+        roots.append(C.sum_tree(lz, sel))
+    say("oracle", len(lz.nodes), "bootstraps")
+    C.evaluate(P, K, lz, threads=oracle.default_threads())
+    for k, (rows, op, c) in enumerate(specs):
+        g = from_dev(P, outs[k])
+        assert np.array_equal(g, C.resolve(P, roots[k])), k
+        pred = (col1[:rows] == c) if op == "eq" else (col1[:rows] < c)
+        assert bits_to_int(dec_bits(P, K, g)) == int((col2[:rows] * pred).sum())
