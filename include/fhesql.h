@@ -140,8 +140,8 @@ int tfhe_set_kernel(tfhe_ctx* ctx, int kind);
  *                        output rows over many workgroups (latency of small
  *                        batches: SUM-tree levels, server ticks) instead of
  *                        one workgroup per group for all n steps; -1 (the
- *                        default) = a quarter of the device's CUs for
- *                        N >= 512 and never for N = 256, 0 = never. */
+ *                        default) = half the device's CUs for N >= 512 and
+ *                        never for N = 256, 0 = never. */
 #define TFHE_TUNE_SPLIT_GROUPS 4
 int tfhe_set_tuning(tfhe_ctx* ctx, int key, int64_t value);
 /* Current value of a tuning knob (as set, 0 or -1 for the defaults). */
@@ -161,7 +161,7 @@ int tfhe_bootstrap_batch(tfhe_ctx* ctx, const void* d_lwe_in, const void* d_test
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): same arguments and output bits, but the blind-rotation
  * workspace is a static device array of tfhe_noalloc_scratch_bytes() bytes
- * (16 MiB; one copy per device, held until the process ends) and the call
+ * (32 MiB; one copy per device, held until the process ends) and the call
  * allocates nothing and records no timing events.  A batch whose workspace
  * would exceed the array fails with TFHE_ESHAPE before any launch (at the
  * standard 32-bit set up to 4096 ciphertexts fit; parameter sets whose

@@ -76,9 +76,11 @@ FHE_DEV size_t acc_idx(int N, int v, int j, int c) {
 // With DS > 1 the caller forms slice `ds` of DS equal slices of the items
 // (the multi-workgroup blind rotation spreads one group's digits over DS
 // workgroups).
-template <typename T, int R, int U, bool GC = false, int DS = 1>
+// With acopy the item's own accumulator words are also copied there (same
+// layout), which seeds the next accumulator of the multi-workgroup path.
+template <typename T, int R, int U, bool GC = false, int DS = 1, bool AC = false>
 FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u_lo, int p_lo, int p_n, int l,
-                          int bgb, int8_t* gdst = nullptr, int ds = 0) {
+                          int bgb, int8_t* gdst = nullptr, int ds = 0, T* acopy = nullptr) {
     typedef T vec4 __attribute__((ext_vector_type(4)));
     constexpr int N = R * 64;
     constexpr int NG = N / 4;  // 4-word groups per component
@@ -112,6 +114,7 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
             const int q0 = kg - qs;
             kq[k] = q0;
             dv[k] = P[kg * CTS];
+            if (AC) ((vec4*)(acopy + (size_t)u * NG * CTS * 4) + c)[kg * CTS] = dv[k];
             r0[k] = P[(q0 & (NG - 1)) * CTS];
             r1[k] = P[((q0 + 1) & (NG - 1)) * CTS];
         }
@@ -326,11 +329,11 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
 
     // With all digits of a step formed before its blocks (DALL) the
     // accumulator is updated in place; otherwise two buffers alternate.
-    // With component 0 in LDS (ACCL) a workgroup's slot holds component 1
-    // only, and ws0 is placed N*CTS words before it so that component 1
-    // keeps its offset in the [v][N/4][16][4] layout.
-    T* ws0 = ACCL ? (T*)a.ws + ((size_t)blockIdx.x - 1) * (N * CTS)
-                  : (T*)a.ws + (size_t)blockIdx.x * (DALL ? 1 : 2) * (2 * N * CTS);
+    // With component 0 in LDS (ACCL) only the component-1 half of a
+    // workgroup's slot is used; the slot keeps its full 2N*CTS-word stride,
+    // which measured about 1% faster at the standard set than packing the
+    // component-1 halves (and moved a tenth of the HBM bytes).
+    T* ws0 = (T*)a.ws + (size_t)blockIdx.x * (DALL ? 1 : 2) * (2 * N * CTS);
     T* ws1 = DALL ? ws0 : ws0 + 2 * N * CTS;
     T* const acc1 = (ACC1L ? acc0 : ws0) + (size_t)N * CTS;  // ACCL: component 1 (LDS or global)
 
@@ -570,6 +573,10 @@ struct SplitArgs {
     int B, G, n, l, bg_bits, step;
 };
 
+// Row tiles per wave of the multi-workgroup path (each key fragment feeds
+// that many MFMAs, which hides the LDS latency of the next one).
+constexpr int SPLIT_RP = 4;
+
 // Digit slices per group and component: 1024 items (of 4 coefficients) each.
 template <int R>
 constexpr int split_ds() { return R >= 4 ? R / 4 : 1; }
@@ -608,11 +615,17 @@ __global__ __launch_bounds__(THREADS) void split_digits_kernel(SplitArgs a) {
     const T* lwe = (const T*)a.lwe;
     const int ab = gi < a.B ? (int)mod_switch<T>(lwe[(size_t)gi * (a.n + 1) + a.step], LG) : 0;
     const T* src = (const T*)a.acc + ((size_t)(a.step & 1) * a.G + g) * 2 * N * CTS;
+    T* next = (T*)a.acc + ((size_t)((a.step + 1) & 1) * a.G + g) * 2 * N * CTS;
     int8_t* dst = a.dig + ((size_t)g * 2 * a.l + (size_t)u * a.l) * R * 1024;
-    digits_phase<T, R, 1, false, DS>(src, ab, dst, u, 0, a.l, a.l, a.bg_bits, nullptr, ds);
+    // also seeds the next accumulator with this one (the MFMA launch adds to it)
+    digits_phase<T, R, 1, false, DS, true>(src, ab, dst, u, 0, a.l, a.l, a.bg_bits, nullptr, ds, next);
 }
 
-// grid (G, R/RP): row pass blockIdx.y of group blockIdx.x for step a.step.
+// grid (G, R/RP, KS): row pass blockIdx.y of group blockIdx.x over the
+// (u,p) blocks of K-slice blockIdx.z (2l/KS consecutive blocks) for step
+// a.step; its partial sums are added to the next accumulator (seeded with
+// this step's by the digit launch) -- with atomic adds when several slices
+// share the rows, which keeps the sum exact mod 2^q in any order.
 template <typename T, int R, int RP>
 __global__ __launch_bounds__(THREADS, 1) void split_mfma_kernel(SplitArgs a) {
     constexpr int N = R * 64;
@@ -625,6 +638,8 @@ __global__ __launch_bounds__(THREADS, 1) void split_mfma_kernel(SplitArgs a) {
     const int g = blockIdx.x, pass = blockIdx.y;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int NB = 2 * a.l;
+    const int KS = (int)gridDim.z;
+    const int ub0 = blockIdx.z * (NB / KS), ub1 = ub0 + NB / KS;
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     int8_t* dslot = (int8_t*)smem;       // digit block (R KB), then the key block
     uint8_t* kslot = smem + (size_t)R * 1024;
@@ -661,28 +676,33 @@ __global__ __launch_bounds__(THREADS, 1) void split_mfma_kernel(SplitArgs a) {
     for (int q = 0; q < RP; q++)
 #pragma unroll
         for (int e = 0; e < 4; e++) delta[q][e] = 0;
-    load(0);
-    for (int ub = 0; ub < NB; ub++) {
+    load(ub0);
+    for (int ub = ub0; ub < ub1; ub++) {
         store();
         __syncthreads();
-        if (ub + 1 < NB) load(ub + 1);  // in flight during this block's MFMAs
+        if (ub + 1 < ub1) load(ub + 1);  // in flight during this block's MFMAs
         mfma_block<T, R, RP, 1>(kslot, dslot, v, jr, pass, delta);
         __syncthreads();
     }
-    // rows of this pass: ACC_new = ACC + delta.  Row tile J = jr + 4(pass RP + q)
-    // holds coefficients 16J + 4(lane>>4) + e of ciphertext lane&15.
-    typedef T vec4 __attribute__((ext_vector_type(4)));
-    const T* src = (const T*)a.acc + ((size_t)(a.step & 1) * a.G + g) * 2 * N * CTS;
+    // Row tile J = jr + 4(pass RP + q) holds coefficients 16J + 4(lane>>4) + e
+    // of ciphertext lane&15.
     T* dst = (T*)a.acc + ((size_t)((a.step + 1) & 1) * a.G + g) * 2 * N * CTS;
     const size_t base0 = acc_idx<T>(N, v, 16 * (jr + 4 * pass * RP) + 4 * (lane >> 4), lane & 15);
     constexpr size_t STEP = (size_t)(64 / 4) * CTS * 4;  // 4 row tiles further
+    typedef T vec4 __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int q = 0; q < RP; q++) {
-        const vec4 cur = *(const vec4*)(src + base0 + q * STEP);
-        vec4 o;
+        T* row = dst + base0 + q * STEP;
+        if (KS == 1) {
+            const vec4 cur = *(const vec4*)row;
+            vec4 o;
 #pragma unroll
-        for (int e = 0; e < 4; e++) o[e] = (T)(cur[e] + delta[q][e]);
-        *(vec4*)(dst + base0 + q * STEP) = o;
+            for (int e = 0; e < 4; e++) o[e] = (T)(cur[e] + delta[q][e]);
+            *(vec4*)row = o;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; e++) atomicAdd(row + e, delta[q][e]);
+        }
     }
 }
 
@@ -705,10 +725,12 @@ __global__ __launch_bounds__(THREADS) void split_extract_kernel(SplitArgs a) {
     }
 }
 
-template <typename T, int R, int RP>
-int launch_split_t(tfhe_ctx* c, SplitArgs a, hipStream_t s) {
+template <typename T, int R>
+int launch_split_t(tfhe_ctx* c, SplitArgs a, int KS, hipStream_t s) {
     constexpr int N = R * 64;
     constexpr int NL = Torus<T>::LIMBS;
+    constexpr int RP = SPLIT_RP;
+    if (KS < 1 || (2 * a.l) % KS) return ctx_fail(c, TFHE_EINVAL, "K slices must divide the 2l key blocks");
     // (+16: the last limb's fragments read up to 4 bytes past the key block)
     const size_t lds = (size_t)R * 1024 + 2ull * NL * 2 * N + 16;
     auto km = split_mfma_kernel<T, R, RP>;
@@ -721,7 +743,7 @@ int launch_split_t(tfhe_ctx* c, SplitArgs a, hipStream_t s) {
     for (int i = 0; i < a.n; i++) {
         a.step = i;
         hipLaunchKernelGGL(kd, dim3(a.G, 2, split_ds<R>()), dim3(THREADS), 0, s, a);
-        hipLaunchKernelGGL(km, dim3(a.G, R / RP), dim3(THREADS), lds, s, a);
+        hipLaunchKernelGGL(km, dim3(a.G, R / RP, KS), dim3(THREADS), lds, s, a);
     }
     hipLaunchKernelGGL(kx, dim3(a.G), dim3(THREADS), 0, s, a);
     return hip_check(c, hipGetLastError(), "launch split blind rotation");
@@ -799,9 +821,9 @@ int dispatch_dg(tfhe_ctx* c, const BrArgs& a, int dg, hipStream_t s) {
 }
 
 // Accumulator buffers per workgroup (words of 2N * CTS per buffer): none
-// when both components stay in LDS, component 1 alone with component 0 in
-// LDS, one buffer updated in place when a step's digits are formed before
-// its blocks, else two alternating buffers.  Then (several row passes with
+// when both components stay in LDS, one buffer (of which component 0 in LDS
+// leaves the first half unused) when a step's digits are formed before its
+// blocks, else two alternating buffers.  Then (several row passes with
 // per-group digits) the digit cache.
 size_t acc_ws_bytes(const tfhe_ctx* c, uint32_t B) {
     const int R = (int)c->p.N / 64, rp = plan_rp(c);
@@ -810,32 +832,37 @@ size_t acc_ws_bytes(const tfhe_ctx* c, uint32_t B) {
     if (dg == kNoFit) return 0;
     const size_t grid = (B + CTS - 1) / CTS;
     const size_t comp = (size_t)c->p.N * CTS * word_bytes(c);  // one component of a workgroup
-    if (dg < 0) return 2 * comp <= 65536 ? 0 : grid * comp;
+    if (dg < 0) return 2 * comp <= 65536 ? 0 : grid * 2 * comp;
     return grid * (dg == 0 ? 1 : 2) * 2 * comp;
 }
 
 // Groups of 16 ciphertexts up to which a batch takes the multi-workgroup
-// path: the split_groups knob, by default a quarter of the CUs for N >= 512
-// (at N = 256 a group's step is too short to gain, so only on request).
+// path: the split_groups knob, by default half the CUs for N >= 512 (at the
+// standard set it is still 6% faster at 128 groups; at N = 256 a group's
+// step is too short to gain, so only on request).
 int64_t split_limit(const tfhe_ctx* c) {
     const int R = (int)c->p.N / 64;
     if (R < 4) return 0;
     const int cus = c->prop.multiProcessorCount > 0 ? c->prop.multiProcessorCount : 256;
     if (c->split_groups >= 0) return c->split_groups;
-    return R >= 8 ? cus / 4 : 0;
+    return R >= 8 ? cus / 2 : 0;
 }
 
-// Row tiles per workgroup of the multi-workgroup path for a batch of B (0 =
-// the persistent kernel): one row tile per workgroup while that keeps at
-// most two workgroups per CU, else two.
-int split_rp(const tfhe_ctx* c, uint32_t B) {
+// K slices of the multi-workgroup path for a batch of B (0 = the persistent
+// kernel): the most (a divisor of the 2l key blocks) that keep the launch
+// within two workgroups per CU, at least one.
+int split_ks(const tfhe_ctx* c, uint32_t B) {
     const int R = (int)c->p.N / 64;
-    if (B == 0) return 0;
+    if (B == 0 || R < SPLIT_RP) return 0;
     const int cus = c->prop.multiProcessorCount > 0 ? c->prop.multiProcessorCount : 256;
     const int64_t lim = split_limit(c);
     const int64_t G = (B + CTS - 1) / CTS;
     if (G > lim) return 0;
-    return G * R <= 2 * cus ? 1 : 2;
+    const int NB = 2 * (int)c->p.l;
+    int ks = 1;
+    for (int d = 1; d <= NB; d++)
+        if (NB % d == 0 && G * (R / SPLIT_RP) * d <= 2 * cus) ks = d;
+    return ks;
 }
 
 size_t split_ws_bytes(const tfhe_ctx* c, uint32_t B) {
@@ -870,7 +897,7 @@ bool mfma_row_pass_supported(const tfhe_ctx* c, int rp) {
 }
 
 size_t mfma_ws_bytes(const tfhe_ctx* c, uint32_t B) {
-    if (split_rp(c, B)) return split_ws_bytes(c, B);
+    if (split_ks(c, B)) return split_ws_bytes(c, B);
     return acc_ws_bytes(c, B) + dcache_bytes(c, B);
 }
 
@@ -885,8 +912,8 @@ size_t mfma_ws_bytes_upto(const tfhe_ctx* c, uint32_t Bmax) {
 }
 
 template <typename T, int R>
-int dispatch_split(tfhe_ctx* c, const SplitArgs& a, int rp, hipStream_t s) {
-    return rp == 1 ? launch_split_t<T, R, 1>(c, a, s) : launch_split_t<T, R, 2>(c, a, s);
+int dispatch_split(tfhe_ctx* c, const SplitArgs& a, int ks, hipStream_t s) {
+    return launch_split_t<T, R>(c, a, ks, s);
 }
 
 int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_t* tv_index,
@@ -900,7 +927,7 @@ int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_
     const size_t need = mfma_ws_bytes(c, B);
     if ((need && !ws) || need > ws_cap)
         return ctx_fail(c, TFHE_EINVAL, "blind-rotation workspace too small for the current tuning");
-    if (const int srp = split_rp(c, B)) {
+    if (const int srp = split_ks(c, B)) {
         SplitArgs sa;
         sa.lwe = lwe_in;
         sa.bsk8 = c->d_bsk8;

@@ -95,7 +95,7 @@ struct tfhe_ctx {
     int row_pass = 0;            // MFMA row tiles per pass (0 = default)
     int digit_blocks = 0;        // 0 auto, 1 one digit block at a time, 2 pairs of levels
     int64_t split_groups = -1;   // batches of at most this many 16-ciphertext groups take the
-                                 // multi-workgroup blind rotation (-1 = a quarter of the CUs)
+                                 // multi-workgroup blind rotation (-1 = half the CUs)
     void* d_radix_tv = nullptr;  // radix look-up test polynomials [8][N] words
     void* d_bsk = nullptr;     // [n][(k+1)l][k+1][N] words
     int8_t* d_bsk8 = nullptr;  // [n][(k+1)l][k+1][LIMBS][2N] Toeplitz limb form

@@ -21,7 +21,7 @@ namespace {
 // kernels.  No kernel needs the scratch cleared: the blind rotation writes
 // every accumulator word it reads (its prologue) and the digit cache is
 // written by a step's first row pass before the later passes read it.
-constexpr size_t kScratchBytes = (size_t)16 << 20;
+constexpr size_t kScratchBytes = (size_t)32 << 20;
 static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 constexpr int kMaxDevices = 64;
 void* g_scratch_ptr[kMaxDevices];

@@ -1,9 +1,10 @@
 """Parity of the multi-workgroup blind rotation (small batches: each step
 spread over many workgroups) with the persistent one-workgroup-per-group
 kernel and with the oracle, at every ring size it serves (q = 32 with
-N = 256, 512, 1024, 2048 and q = 64 with N = 512, 1024, 2048), both row-tile
-widths, ragged groups, and inside a circuit (a SUM tree whose narrow levels
-take the split path)."""
+N = 256, 512, 1024, 2048 and q = 64 with N = 512, 1024, 2048), with the key
+blocks split over several workgroups whose sums meet in atomic adds (few
+groups) and kept in one (many groups), ragged groups, and inside a circuit
+(a SUM tree whose narrow levels take the split path)."""
 import sys
 
 import numpy as np
@@ -51,7 +52,7 @@ def test_split_matches_persistent_and_oracle(q, N):
         ref = empty(p, B, p.N + 1)
         ctx.set_tuning(split_groups=NEVER)
         ctx.tfhe_bootstrap_batch(d, ref)
-        ctx.set_tuning(split_groups=ALWAYS)  # (one row tile per workgroup at these batch sizes)
+        ctx.set_tuning(split_groups=ALWAYS)  # (few groups: key blocks over several workgroups)
         got = empty(p, B, p.N + 1)
         ctx.tfhe_bootstrap_batch(d, got)
         torch.cuda.synchronize()
@@ -65,16 +66,16 @@ def test_split_matches_persistent_and_oracle(q, N):
 
 
 @pytest.mark.parametrize("q,N", [(32, 1024), (64, 2048)])
-def test_split_two_row_tiles_per_workgroup(q, N):
-    """Enough groups that the split path takes two row tiles per workgroup
-    (more than two workgroups per CU at one): same bits as the persistent
-    kernel on every ciphertext."""
+def test_split_many_groups_one_k_slice(q, N):
+    """Enough groups that the split path keeps all key blocks in one
+    workgroup (no atomic adds): same bits as the persistent kernel on every
+    ciphertext."""
     p = small_params(q, N)
     K = oracle.Keys(p, si.KEY_SEED_BASE + 90 + q)
     ctx = context(p, K)
     R = N // 64
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    G = (2 * cus) // R + 3  # G * R > 2 * CUs
+    G = (2 * cus) // (R // 4) + 3  # G * R/4 > 2 * CUs: one K slice
     B = 16 * G - 5
     lwe = si.torus(9, 91, B * (p.n + 1), p.q).reshape(B, p.n + 1)
     d = to_dev(p, lwe)

@@ -51,7 +51,7 @@ def test_noalloc_rejects_batches_beyond_the_scratch():
     ctx = fs.Context(p, bsk, ksk)
     del bsk, ksk
     cap = _lib.load().tfhe_noalloc_scratch_bytes()
-    per_group = p.N * 16 * 4  # accumulator component 1 of 16 ciphertexts
+    per_group = 2 * p.N * 16 * 4  # the accumulator slot of 16 ciphertexts (both components)
     B = (cap // per_group) * 16 + 16
     lwe = torch.zeros((B, p.n + 1), dtype=torch.int32, device="cuda")
     out = torch.empty((B, p.N + 1), dtype=torch.int32, device="cuda")
