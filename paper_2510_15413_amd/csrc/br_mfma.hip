@@ -89,23 +89,41 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
     const int it0 = ds * ITEMS;
     constexpr int IPT = (ITEMS + THREADS - 1) / THREADS;
     constexpr int G = IPT < 4 ? IPT : 4;
-    const int lb = l * bgb;
-    const uint32_t bgm = (1u << bgb) - 1;
+    constexpr int Q = Torus<T>::Q;
+    // Level p of the balanced decomposition of x is field p of
+    // y = round_top(x, l*bgb) + off, minus half (off = half at every level).
+    // With F = off << shr (shr = Q - l*bgb >= 1, as l*bgb <= 31), the word
+    // z = (x + 2^(shr-1) + F) ^ F holds field p of y with its top bit flipped
+    // at bit shr + (l-1-p)*bgb, and that field read as a signed bgb-bit
+    // number is the digit (t ^ half = t - half mod 2^bgb, sign in the top bit).
+    const int shr = Q - l * bgb;
     const int half = 1 << (bgb - 1);
     uint32_t off = 0;
     for (int p = 0; p < l; p++) off += (uint32_t)half << (p * bgb);
-    const int c = threadIdx.x & (CTS - 1);  // fixed per thread (THREADS % 16 == 0); ab is its abar_i
+    const T F = (T)off << shr;
+    const T C = ((T)1 << (shr - 1)) + F;
+    // the fields sit in the word's low half at q = 32, in its high half at q = 64
+    const int fb = Q == 32 ? shr : shr - 32;
+    // the item addresses below do not change from step to step; an opaque
+    // thread index keeps them from being hoisted out of the caller's step
+    // loop (held there they would crowd out the MFMA phase's registers)
+    int tix = threadIdx.x;
+    __asm__ volatile("" : "+v"(tix));
+    const int c = tix & (CTS - 1);  // fixed per thread (THREADS % 16 == 0); ab is its abar_i
     const int neg = ab >= N;
     const int es = neg ? ab - N : ab;
-    // coefficient 4kg+e reads rotated index 4kg+e-es: group kg-qs (+1), lane sh
+    // coefficient 4kg+e reads rotated index 4kg+e-es: group kg-qs (+1), word e+sh
     const int sh = (4 - (es & 3)) & 3;
     const int qs = (es + 3) >> 2;  // 4kg - es = 4(kg - qs) + sh
+    const bool s1 = (sh & 1) != 0, s2 = (sh & 2) != 0;
+    // word e+sh lies in the second group for e = 1 (sh = 3), 2 (sh >= 2), 3 (sh >= 1)
+    const bool hi1 = sh == 3, hi2 = s2, hi3 = sh != 0;
     for (int k0 = 0; k0 < IPT; k0 += G) {
         vec4 dv[G], r0[G], r1[G];
         int kq[G];
 #pragma unroll
         for (int k = 0; k < G; k++) {
-            const int it = threadIdx.x + (k0 + k) * THREADS;
+            const int it = tix + (k0 + k) * THREADS;
             if (ITEMS % THREADS != 0 && it >= ITEMS) continue;
             const int rest = (it0 + it) >> 4;
             const int kg = rest & (NG - 1);
@@ -120,7 +138,7 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
         }
 #pragma unroll
         for (int k = 0; k < G; k++) {
-            const int it = threadIdx.x + (k0 + k) * THREADS;
+            const int it = tix + (k0 + k) * THREADS;
             if (ITEMS % THREADS != 0 && it >= ITEMS) continue;
             const int rest = (it0 + it) >> 4;
             const int kg = rest & (NG - 1);
@@ -128,32 +146,35 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
             // negacyclic sign: a group below zero wraps with a sign flip
             const bool n0 = (kq[k] < 0) != (neg != 0);
             const bool n1 = (kq[k] + 1 < 0) != (neg != 0);
-            uint32_t y[4];
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int x = e + sh;  // 0..6
-                T v;
-                bool ng;
-                if (x < 4) {
-                    v = x == 0 ? r0[k][0] : x == 1 ? r0[k][1] : x == 2 ? r0[k][2] : r0[k][3];
-                    ng = n0;
-                } else {
-                    v = x == 4 ? r1[k][0] : x == 5 ? r1[k][1] : r1[k][2];
-                    ng = n1;
-                }
-                const T rv = ng ? (T)(0 - v) : v;
-                y[e] = (uint32_t)round_top<T>((T)(rv - dv[k][e]), lb) + off;
-            }
+            // word e+sh of the 7 words r0[0..3], r1[0..2]: two selects by the
+            // bits of sh (named values, not an array: an indexed array would
+            // be placed in scratch memory)
+            const T q0w = s1 ? r0[k][1] : r0[k][0], q1w = s1 ? r0[k][2] : r0[k][1];
+            const T q2w = s1 ? r0[k][3] : r0[k][2], q3w = s1 ? r1[k][0] : r0[k][3];
+            const T q4w = s1 ? r1[k][1] : r1[k][0], q5w = s1 ? r1[k][2] : r1[k][1];
+            const T v0 = s2 ? q2w : q0w, v1 = s2 ? q3w : q1w, v2 = s2 ? q4w : q2w, v3 = s2 ? q5w : q3w;
+            auto field_word = [&](T v, bool ng, T d) -> uint32_t {
+                const T wv = (T)(C - d);
+                const T z = (T)((ng ? (T)(wv - v) : (T)(wv + v)) ^ F);
+                return Q == 32 ? (uint32_t)z : (uint32_t)((uint64_t)z >> 32);
+            };
+            uint32_t zz[4];
+            zz[0] = field_word(v0, n0, dv[k][0]);
+            zz[1] = field_word(v1, hi1 ? n1 : n0, dv[k][1]);
+            zz[2] = field_word(v2, hi2 ? n1 : n0, dv[k][2]);
+            zz[3] = field_word(v3, hi3 ? n1 : n0, dv[k][3]);
             const int j0 = 4 * kg;
             const int ch = j0 >> 6, g = (j0 >> 4) & 3, bo = j0 & 15;
             for (int p = p_lo; p < p_lo + p_n; p++) {
-                const int shp = (l - 1 - p) * bgb;
-                uint32_t packed = 0;
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const int d = (int)((y[e] >> shp) & bgm) - half;
-                    packed |= ((uint32_t)(d & 0xFF)) << (8 * e);
-                }
+                const int pos = fb + (l - 1 - p) * bgb;
+                const int d0 = __builtin_amdgcn_sbfe((int)zz[0], pos, bgb);
+                const int d1 = __builtin_amdgcn_sbfe((int)zz[1], pos, bgb);
+                const int d2 = __builtin_amdgcn_sbfe((int)zz[2], pos, bgb);
+                const int d3 = __builtin_amdgcn_sbfe((int)zz[3], pos, bgb);
+                // low bytes of the four digits, coefficient e in byte e
+                const uint32_t p01 = __builtin_amdgcn_perm((uint32_t)d1, (uint32_t)d0, 0x0C0C0400u);
+                const uint32_t p23 = __builtin_amdgcn_perm((uint32_t)d3, (uint32_t)d2, 0x0C0C0400u);
+                const uint32_t packed = p01 | (p23 << 16);
                 const int blk = (u - u_lo) * p_n + (p - p_lo);
                 const size_t o = ((size_t)blk * R + ch) * 1024 + (g * 16 + c) * 16 + bo;
                 *(uint32_t*)(dbuf + o) = packed;
@@ -217,6 +238,14 @@ FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr,
             bf[cc] = *(const v4i*)(dblk + (size_t)(cg * CP + cc) * 1024 + lane * 16);
         // one limb: its MFMA products for this block in acc[] (int32, exact)
         auto limb = [&](int m, v4i(&acc)[RP]) {
+            // Issue priority falls limb by limb, so of the two waves sharing a
+            // SIMD the one further along yields to the other (at equal
+            // priority the older wave wins, and the younger one would finish
+            // the block alone, leaving gaps in the matrix pipe).
+            if (m == 0) __builtin_amdgcn_s_setprio(3);
+            else if (m == 1) __builtin_amdgcn_s_setprio(2);
+            else if (m == 2) __builtin_amdgcn_s_setprio(1);
+            else __builtin_amdgcn_s_setprio(0);
             const uint8_t* S = kslot + (KC == 4 ? (size_t)sh0 * KCS : 0) + (size_t)(v * NL + m) * (2 * N);
 #pragma unroll
             for (int a = 0; a < RP; a++) acc[a] = v4i{0, 0, 0, 0};
@@ -286,6 +315,7 @@ FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr,
             }
         }
     }
+    __builtin_amdgcn_s_setprio(0);
 }
 
 // DG: digit blocks formed per rotate-diff pass -- 0 all (k+1)l blocks of a
@@ -645,45 +675,51 @@ __global__ __launch_bounds__(THREADS, 1) void split_mfma_kernel(SplitArgs a) {
     uint8_t* kslot = smem + (size_t)R * 1024;
     const uint4* kbase = (const uint4*)a.bsk8 + (size_t)a.step * NB * KU;
     const uint4* dbase = (const uint4*)(a.dig + (size_t)g * NB * R * 1024);
-    uint4 kp[KV], dp[DV];
-    auto load = [&](int ub) {
-#pragma unroll
-        for (int q = 0; q < KV; q++) {
-            const int idx = tid + q * THREADS;
-            if (KU % THREADS == 0 || idx < KU) kp[q] = kbase[(size_t)ub * KU + idx];
-        }
-#pragma unroll
-        for (int q = 0; q < DV; q++) {
-            const int idx = tid + q * THREADS;
-            if (DU % THREADS == 0 || idx < DU) dp[q] = dbase[(size_t)ub * DU + idx];
-        }
-    };
-    auto store = [&]() {
-#pragma unroll
-        for (int q = 0; q < KV; q++) {
-            const int idx = tid + q * THREADS;
-            if (KU % THREADS == 0 || idx < KU) ((uint4*)kslot)[idx] = kp[q];
-        }
-#pragma unroll
-        for (int q = 0; q < DV; q++) {
-            const int idx = tid + q * THREADS;
-            if (DU % THREADS == 0 || idx < DU) ((uint4*)dslot)[idx] = dp[q];
-        }
-    };
+    // Staged through registers as native 4-word vectors: held as HIP's
+    // uint4 across the block loop the arrays were placed in scratch memory,
+    // and each prefetch then waited for its loads at once.
+    typedef uint32_t w4 __attribute__((ext_vector_type(4)));
+    const w4* kbv = (const w4*)kbase;
+    const w4* dbv = (const w4*)dbase;
+    w4 kp[KV], dp[DV];
+#define SPLIT_LOAD(UB)                                                          \
+    do {                                                                        \
+        _Pragma("unroll") for (int q_ = 0; q_ < KV; q_++) {                     \
+            const int idx_ = tid + q_ * THREADS;                                \
+            if (KU % THREADS == 0 || idx_ < KU) kp[q_] = kbv[(size_t)(UB) * KU + idx_]; \
+        }                                                                       \
+        _Pragma("unroll") for (int q_ = 0; q_ < DV; q_++) {                     \
+            const int idx_ = tid + q_ * THREADS;                                \
+            if (DU % THREADS == 0 || idx_ < DU) dp[q_] = dbv[(size_t)(UB) * DU + idx_]; \
+        }                                                                       \
+    } while (0)
+#define SPLIT_STORE()                                                           \
+    do {                                                                        \
+        _Pragma("unroll") for (int q_ = 0; q_ < KV; q_++) {                     \
+            const int idx_ = tid + q_ * THREADS;                                \
+            if (KU % THREADS == 0 || idx_ < KU) ((w4*)kslot)[idx_] = kp[q_]; \
+        }                                                                       \
+        _Pragma("unroll") for (int q_ = 0; q_ < DV; q_++) {                     \
+            const int idx_ = tid + q_ * THREADS;                                \
+            if (DU % THREADS == 0 || idx_ < DU) ((w4*)dslot)[idx_] = dp[q_]; \
+        }                                                                       \
+    } while (0)
     const int v = wave >> 2, jr = wave & 3;
     T delta[RP][4];
 #pragma unroll
     for (int q = 0; q < RP; q++)
 #pragma unroll
         for (int e = 0; e < 4; e++) delta[q][e] = 0;
-    load(ub0);
+    SPLIT_LOAD(ub0);
     for (int ub = ub0; ub < ub1; ub++) {
-        store();
+        SPLIT_STORE();
         __syncthreads();
-        if (ub + 1 < ub1) load(ub + 1);  // in flight during this block's MFMAs
+        if (ub + 1 < ub1) SPLIT_LOAD(ub + 1);  // in flight during this block's MFMAs
         mfma_block<T, R, RP, 1>(kslot, dslot, v, jr, pass, delta);
         __syncthreads();
     }
+#undef SPLIT_LOAD
+#undef SPLIT_STORE
     // Row tile J = jr + 4(pass RP + q) holds coefficients 16J + 4(lane>>4) + e
     // of ciphertext lane&15.
     T* dst = (T*)a.acc + ((size_t)((a.step + 1) & 1) * a.G + g) * 2 * N * CTS;
