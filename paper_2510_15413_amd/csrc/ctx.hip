@@ -205,13 +205,19 @@ extern "C" int tfhe_ctx_create(const tfhe_params* p, const void* bsk, size_t bsk
     const size_t polys = (size_t)p->n * (p->k + 1) * p->l * (p->k + 1);
     int rc = TFHE_OK;
     const hipMemcpyKind kind = keys_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    // KSK rows start on 128-byte lines, so that a key-switch workgroup's
+    // 16-word slice of a row touches whole lines of its own
+    c->ks_row = ((p->n + 1) * wb + 127) / 128 * 128 / wb;
+    const size_t ks_rows = (size_t)p->k * p->N * p->ks_t * ((size_t)1 << p->ks_base_bits);
     if ((rc = hip_check(c, hipMalloc(&c->d_bsk, bsk_bytes), "hipMalloc bsk")) ||
-        (rc = hip_check(c, hipMalloc(&c->d_ksk, ksk_bytes), "hipMalloc ksk")) ||
+        (rc = hip_check(c, hipMalloc(&c->d_ksk, ks_rows * c->ks_row * wb), "hipMalloc ksk")) ||
         (rc = hip_check(c, hipMalloc((void**)&c->d_bsk8, polys * NL * 2 * p->N), "hipMalloc bsk8")) ||
         (rc = hip_check(c, hipMalloc(&c->d_gate_tv, p->N * wb), "hipMalloc testv")) ||
         (rc = hip_check(c, hipMalloc(&c->d_false, (p->n + 1) * wb), "hipMalloc false")) ||
         (rc = hip_check(c, hipMemcpy(c->d_bsk, bsk, bsk_bytes, kind), "copy bsk")) ||
-        (rc = hip_check(c, hipMemcpy(c->d_ksk, ksk, ksk_bytes, kind), "copy ksk"))) {
+        (rc = hip_check(c, hipMemset(c->d_ksk, 0, ks_rows * c->ks_row * wb), "clear ksk")) ||
+        (rc = hip_check(c, hipMemcpy2D(c->d_ksk, c->ks_row * wb, ksk, (p->n + 1) * wb, (p->n + 1) * wb, ks_rows, kind),
+                        "copy ksk"))) {
         tfhe_ctx_destroy(c);
         return rc;
     }

@@ -13,6 +13,14 @@
 // coefficients per barrier), and each lane reads the row its digit selects
 // with 16-byte LDS reads.  Rows are padded by 16 bytes so that the
 // lanes' distinct rows fall on different bank groups.
+//
+// Placement.  Workgroups are dealt round-robin to the 8 XCDs, each with its
+// own L2.  The grid is one-dimensional and a workgroup's (word tile,
+// ciphertext group) is taken from a tile-major or group-major order cut into
+// 8 contiguous runs, one per XCD: tile-major when the table is larger than
+// the batch's inputs (each XCD then fetches only its tiles' columns of the
+// table, whose rows start on 128-byte lines), group-major otherwise (each XCD
+// fetches only its groups' inputs).
 #include "fhesql_internal.h"
 
 namespace {
@@ -34,10 +42,16 @@ struct Vec16<uint64_t> {
     static constexpr int N = 2;
 };
 
+struct KsPlace {
+    int tiles, groups;  // word tiles and ciphertext groups
+    int per;            // workgroups per XCD run (the grid is 8 * per)
+    int tile_major;     // 1: runs of consecutive tiles, 0: runs of consecutive groups
+};
+
 template <typename T, int V, int WPW, int P>
 __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict__ big, const T* __restrict__ ksk,
                                                             T* out, const uint64_t* out_ptrs, int B, int n, int kN,
-                                                            int t, int bb) {
+                                                            int t, int bb, int ks_row, KsPlace pl) {
     typedef typename Vec16<T>::type vec;
     constexpr int EV = Vec16<T>::N;          // words per 16-byte read
     constexpr int RS = WPW + EV;             // LDS row stride in words (16-byte pad)
@@ -45,9 +59,14 @@ __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict_
     T* tab = (T*)smem;                       // [2][P][t*V][RS]
     const int TS = t * V * RS;               // words per coefficient
     const int tid = threadIdx.x;
-    const int c = blockIdx.y * TC + tid;
-    const int w0 = blockIdx.x * WPW;
-    const size_t row = (size_t)(n + 1);
+    // workgroup L runs on XCD L % 8 as the (L / 8)-th of that XCD's run
+    const int z = (int)(blockIdx.x % 8) * pl.per + (int)(blockIdx.x / 8);
+    if (z >= pl.tiles * pl.groups) return;  // padding of the last run
+    const int tile = pl.tile_major ? z / pl.groups : z % pl.tiles;
+    const int grp = pl.tile_major ? z % pl.groups : z / pl.tiles;
+    const int c = grp * TC + tid;
+    const int w0 = tile * WPW;
+    const size_t row = (size_t)ks_row;  // table row stride in words
     const int E = t * V * WPW;               // staged words per coefficient
     const int tb = t * bb;
     const bool live = c < B;
@@ -145,7 +164,7 @@ __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict_
         }
     }
     if (!live) return;
-    T* dst = out_ptrs ? (T*)(uintptr_t)out_ptrs[c] : out + (size_t)c * row;
+    T* dst = out_ptrs ? (T*)(uintptr_t)out_ptrs[c] : out + (size_t)c * (n + 1);
 #pragma unroll
     for (int k = 0; k < WPW; k++)
         if (w0 + k <= n) dst[w0 + k] = acc[k];
@@ -159,8 +178,14 @@ int launch_p(tfhe_ctx* c, const T* big, T* out, const uint64_t* out_ptrs, uint32
     auto k = keyswitch_kernel<T, V, WPW, P>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return hip_check(c, e, "hipFuncSetAttribute(keyswitch)");
-    dim3 grid((n + 1 + WPW - 1) / WPW, (B + TC - 1) / TC);
-    hipLaunchKernelGGL(k, grid, dim3(THREADS), lds, s, big, (const T*)c->d_ksk, out, out_ptrs, (int)B, n, kN, t, bb);
+    KsPlace pl;
+    pl.tiles = (n + 1 + WPW - 1) / WPW;
+    pl.groups = (int)((B + TC - 1) / TC);
+    pl.per = (pl.tiles * pl.groups + 7) / 8;
+    const double table = (double)kN * t * V * (n + 1), inputs = (double)B * (kN + 1);
+    pl.tile_major = table > inputs ? 1 : 0;
+    hipLaunchKernelGGL(k, dim3(8 * pl.per), dim3(THREADS), lds, s, big, (const T*)c->d_ksk, out, out_ptrs, (int)B, n,
+                       kN, t, bb, (int)c->ks_row, pl);
     return hip_check(c, hipGetLastError(), "launch keyswitch");
 }
 
