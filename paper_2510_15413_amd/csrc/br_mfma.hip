@@ -118,34 +118,40 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
     const bool s1 = (sh & 1) != 0, s2 = (sh & 2) != 0;
     // word e+sh lies in the second group for e = 1 (sh = 3), 2 (sh >= 2), 3 (sh >= 1)
     const bool hi1 = sh == 3, hi2 = s2, hi3 = sh != 0;
+    // all ones when the rotation exponent is at least N (X^N = -1)
+    const T negm = neg ? ~(T)0 : (T)0;
+    // item it = tix + k*THREADS covers group (it0 + it) >> 4 of the U
+    // components (all unsigned, so that the divisions are shifts)
+    const unsigned rest0 = ((unsigned)it0 + (unsigned)tix) >> 4;
+    constexpr unsigned RSTEP = THREADS / CTS;
+    const vec4* Pc = (const vec4*)src + c;
     for (int k0 = 0; k0 < IPT; k0 += G) {
         vec4 dv[G], r0[G], r1[G];
         int kq[G];
 #pragma unroll
         for (int k = 0; k < G; k++) {
-            const int it = tix + (k0 + k) * THREADS;
-            if (ITEMS % THREADS != 0 && it >= ITEMS) continue;
-            const int rest = (it0 + it) >> 4;
-            const int kg = rest & (NG - 1);
-            const int u = u_lo + rest / NG;
-            const vec4* P = (const vec4*)(src + (size_t)u * NG * CTS * 4) + c;
-            const int q0 = kg - qs;
+            if (ITEMS % THREADS != 0 && (unsigned)tix + (unsigned)(k0 + k) * THREADS >= (unsigned)ITEMS) continue;
+            const unsigned rest = rest0 + (unsigned)(k0 + k) * RSTEP;
+            const unsigned kg = rest & (NG - 1);
+            const unsigned ub = (U == 1 ? 0u : rest / NG) + (unsigned)u_lo;
+            const vec4* P = Pc + (size_t)ub * NG * CTS;
+            const int q0 = (int)kg - qs;
             kq[k] = q0;
             dv[k] = P[kg * CTS];
-            if (AC) ((vec4*)(acopy + (size_t)u * NG * CTS * 4) + c)[kg * CTS] = dv[k];
-            r0[k] = P[(q0 & (NG - 1)) * CTS];
-            r1[k] = P[((q0 + 1) & (NG - 1)) * CTS];
+            if (AC) ((vec4*)acopy + c + (size_t)ub * NG * CTS)[kg * CTS] = dv[k];
+            r0[k] = P[(unsigned)(q0 & (NG - 1)) * CTS];
+            r1[k] = P[(unsigned)((q0 + 1) & (NG - 1)) * CTS];
         }
 #pragma unroll
         for (int k = 0; k < G; k++) {
-            const int it = tix + (k0 + k) * THREADS;
-            if (ITEMS % THREADS != 0 && it >= ITEMS) continue;
-            const int rest = (it0 + it) >> 4;
-            const int kg = rest & (NG - 1);
-            const int u = u_lo + rest / NG;
-            // negacyclic sign: a group below zero wraps with a sign flip
-            const bool n0 = (kq[k] < 0) != (neg != 0);
-            const bool n1 = (kq[k] + 1 < 0) != (neg != 0);
+            if (ITEMS % THREADS != 0 && (unsigned)tix + (unsigned)(k0 + k) * THREADS >= (unsigned)ITEMS) continue;
+            const unsigned rest = rest0 + (unsigned)(k0 + k) * RSTEP;
+            const int kg = (int)(rest & (NG - 1));
+            const int u = (U == 1 ? 0 : (int)(rest / NG)) + u_lo;
+            // negacyclic sign as a mask (all ones: negate): a group below
+            // zero wraps with a sign flip, on top of the exponent's
+            const T m0 = (T)(int64_t)(kq[k] >> 31) ^ negm;
+            const T m1 = (T)(int64_t)((kq[k] + 1) >> 31) ^ negm;
             // word e+sh of the 7 words r0[0..3], r1[0..2]: two selects by the
             // bits of sh (named values, not an array: an indexed array would
             // be placed in scratch memory)
@@ -153,18 +159,20 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
             const T q2w = s1 ? r0[k][3] : r0[k][2], q3w = s1 ? r1[k][0] : r0[k][3];
             const T q4w = s1 ? r1[k][1] : r1[k][0], q5w = s1 ? r1[k][2] : r1[k][1];
             const T v0 = s2 ? q2w : q0w, v1 = s2 ? q3w : q1w, v2 = s2 ? q4w : q2w, v3 = s2 ? q5w : q3w;
-            auto field_word = [&](T v, bool ng, T d) -> uint32_t {
-                const T wv = (T)(C - d);
-                const T z = (T)((ng ? (T)(wv - v) : (T)(wv + v)) ^ F);
+            // (v ^ m) - m is v or -v
+            auto field_word = [&](T v, T m, T d) -> uint32_t {
+                const T z = (T)(((T)(C - d) + (T)((T)(v ^ m) - m)) ^ F);
                 return Q == 32 ? (uint32_t)z : (uint32_t)((uint64_t)z >> 32);
             };
             uint32_t zz[4];
-            zz[0] = field_word(v0, n0, dv[k][0]);
-            zz[1] = field_word(v1, hi1 ? n1 : n0, dv[k][1]);
-            zz[2] = field_word(v2, hi2 ? n1 : n0, dv[k][2]);
-            zz[3] = field_word(v3, hi3 ? n1 : n0, dv[k][3]);
-            const int j0 = 4 * kg;
-            const int ch = j0 >> 6, g = (j0 >> 4) & 3, bo = j0 & 15;
+            zz[0] = field_word(v0, m0, dv[k][0]);
+            zz[1] = field_word(v1, hi1 ? m1 : m0, dv[k][1]);
+            zz[2] = field_word(v2, hi2 ? m1 : m0, dv[k][2]);
+            zz[3] = field_word(v3, hi3 ? m1 : m0, dv[k][3]);
+            // coefficients 4kg..4kg+3: chunk kg/16, lane group (kg/4)%4, bytes 4(kg%4)..
+            const unsigned ukg = (unsigned)kg;
+            const unsigned obase = (ukg >> 4) * 1024u + ((ukg >> 2) & 3u) * 256u + (unsigned)c * 16u + (ukg & 3u) * 4u +
+                                   (unsigned)((u - u_lo) * p_n) * (unsigned)(R * 1024);
             for (int p = p_lo; p < p_lo + p_n; p++) {
                 const int pos = fb + (l - 1 - p) * bgb;
                 const int d0 = __builtin_amdgcn_sbfe((int)zz[0], pos, bgb);
@@ -175,8 +183,7 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
                 const uint32_t p01 = __builtin_amdgcn_perm((uint32_t)d1, (uint32_t)d0, 0x0C0C0400u);
                 const uint32_t p23 = __builtin_amdgcn_perm((uint32_t)d3, (uint32_t)d2, 0x0C0C0400u);
                 const uint32_t packed = p01 | (p23 << 16);
-                const int blk = (u - u_lo) * p_n + (p - p_lo);
-                const size_t o = ((size_t)blk * R + ch) * 1024 + (g * 16 + c) * 16 + bo;
+                const unsigned o = obase + (unsigned)(p - p_lo) * (unsigned)(R * 1024);
                 *(uint32_t*)(dbuf + o) = packed;
                 if (GC) *(uint32_t*)(gdst + o) = packed;
             }
