@@ -449,6 +449,12 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     // the global buffer; the branch is wave-uniform and keeps each access
     // in its own address space (a selected pointer would be a flat access)
     const bool rows_lds = ACCL && (v == 0 || ACC1L);
+    // ACCL without room for component 1 in LDS: component 0's LDS region is
+    // dead from the end of its digit phase to the end of the step, so the
+    // component-1 waves park their rows there for the component-1 digit
+    // phase (no global round trip); they reach global memory only at the end
+    constexpr bool PARK = ACCL && !ACC1L && REGACC;
+    const size_t rbase0 = rbase - (size_t)v * N * CTS;  // the same rows in component 0's layout
     T accr[REGACC ? RP : 1][4];
     if (REGACC) {
         auto get = [&](const T* base) {
@@ -483,8 +489,20 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
                     // digits of component ub/l (its MFMA blocks of the last
                     // component ended with a barrier)
                     if (ub == 0) digits_phase<T, R, 1>(acc0, ab, dbuf, 0, 0, l, l, a.bg_bits);
-                    else digits_phase<T, R, 1>(acc1, ab, dbuf, 0, 0, l, l, a.bg_bits);
+                    else digits_phase<T, R, 1>(PARK ? acc0 : acc1, ab, dbuf, 0, 0, l, l, a.bg_bits);
                     __syncthreads();
+                    if constexpr (PARK) if (ub == 0 && v == 1) {
+                        // this step's component-1 input rows (no fold has touched them yet)
+                        uint32_t ro = (uint32_t)rbase0;
+                        __asm__ volatile("" : "+v"(ro));
+#pragma unroll
+                        for (int q = 0; q < RP; q++) {
+                            vec4 o;
+#pragma unroll
+                            for (int e = 0; e < 4; e++) o[e] = accr[q][e];
+                            *(vec4*)(acc0 + ro + q * STEP4) = o;
+                        }
+                    }
                 }
                 if (!DALL && ub % DG == 0) {
                     int8_t* gc = DCACHE ? a.dcache + ((size_t)blockIdx.x * NB + ub) * R * 1024 : nullptr;
@@ -537,7 +555,7 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
                     }
                 };
                 if (rows_lds) put(acc0);
-                else put(ACCL ? ws0 : dst);
+                else if (!PARK) put(ACCL ? ws0 : dst);
                 continue;
             }
             // dst rows of this pass = src rows + delta (16-byte accesses; all
@@ -572,6 +590,18 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
 
 #undef KEY_LOAD
 #undef KEY_STORE
+    if constexpr (PARK) {
+        if (v == 1) {
+#pragma unroll
+            for (int q = 0; q < RP; q++) {
+                vec4 o;
+#pragma unroll
+                for (int e = 0; e < 4; e++) o[e] = accr[q][e];
+                *(vec4*)(ws0 + rbase + q * STEP4) = o;
+            }
+        }
+        __syncthreads();
+    }
     // ---- sample extraction: a'_0 = A[0], a'_j = -A[N-j], b' = B[0]
     const T* A0 = ACCL ? (const T*)acc0 : src;
     T* out = (T*)a.out;
