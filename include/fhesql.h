@@ -173,7 +173,9 @@ int tfhe_bootstrap_batch_noalloc(tfhe_ctx* ctx, const void* d_lwe_in, const void
                                  void* d_out, uint32_t B, void* hip_stream);
 size_t tfhe_noalloc_scratch_bytes(void);
 
-/* LWE key switching of B big ciphertexts d_in [B][kN+1] to d_out [B][n+1]. */
+/* LWE key switching of B big ciphertexts d_in [B][kN+1] to d_out [B][n+1].
+ * The batch's rounded digits (B*kN 16-bit values, 32-bit when
+ * ks_t*ks_base_bits > 16) are staged in the context's workspace. */
 int tfhe_keyswitch_batch(tfhe_ctx* ctx, const void* d_in, void* d_out, uint32_t B,
                          void* hip_stream);
 

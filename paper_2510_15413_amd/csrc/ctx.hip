@@ -442,7 +442,12 @@ extern "C" int tfhe_keyswitch_batch(tfhe_ctx* c, const void* d_in, void* d_out, 
     if (!c) return TFHE_EINVAL;
     if (B == 0) return TFHE_OK;
     if (!d_in || !d_out) return ctx_fail(c, TFHE_EINVAL, "null ciphertext pointer");
-    return launch_keyswitch(c, d_in, d_out, nullptr, B, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ws_acquire(c, s, ks_digits_bytes(c, B));
+    if (rc) return rc;
+    rc = launch_keyswitch(c, d_in, d_out, nullptr, B, c->ws, c->ws_bytes, s);
+    const int rr = ws_release(c, s);
+    return rc ? rc : rr;
 }
 
 // ------------------------------------------------------- seeded streams

@@ -184,8 +184,11 @@ int launch_blind_rotate(tfhe_ctx* c, const void* lwe_in, const void* testv_table
 size_t blind_rotate_ws_bytes(const tfhe_ctx* c, uint32_t B);
 // Largest blind-rotation workspace of any batch of at most Bmax ciphertexts.
 size_t blind_rotate_ws_bytes_upto(const tfhe_ctx* c, uint32_t Bmax);
+// dig: device buffer of at least ks_digits_bytes(c, B) bytes that the key
+// switch fills with the batch's rounded digits before it reads them.
 int launch_keyswitch(tfhe_ctx* c, const void* big_in, void* out, const uint64_t* out_ptrs,
-                     uint32_t B, hipStream_t s);
+                     uint32_t B, void* dig, size_t dig_cap, hipStream_t s);
+size_t ks_digits_bytes(const tfhe_ctx* c, uint32_t B);
 int launch_combine(tfhe_ctx* c, const Segment* d_segs, const uint32_t* d_seg_start,
                    int nseg, uint32_t total, void* lwe_out, uint64_t* out_ptrs,
                    int32_t* tv_index, hipStream_t s);

@@ -2,6 +2,14 @@
 // out = (0^n, b') - sum_{i<kN} sum_{j<t} KSK[i][j][v_ij], where v_ij is the
 // j-th most significant base-2^b digit of a'_i rounded (ties up) to t*b bits.
 //
+// Digits.  A pre-pass rounds every mask coefficient a'_i of the batch to its
+// top t*b bits once and stores them coefficient-major, dig[i][c] (16-bit
+// when t*b <= 16, else 32-bit): the word tiles of one ciphertext group then
+// read one coalesced row of digits per coefficient instead of each tile
+// re-reading (and re-rounding) the strided full-width words of every
+// ciphertext, which halves or quarters the bytes each XCD pulls per tile
+// and keeps them in L2 while the tiles that share them run.
+//
 // Mapping.  Lanes are ciphertexts: a workgroup of 4 waves owns 256
 // ciphertexts (64 per wave) and a tile of WPW output words, and every lane
 // accumulates those WPW words of its own ciphertext in registers.  The digit
@@ -42,16 +50,39 @@ struct Vec16<uint64_t> {
     static constexpr int N = 2;
 };
 
+// Rounded digits of a 64 x 64 block (ciphertexts x coefficients): rows of
+// the ciphertexts are read coalesced, turned in LDS, and written as rows of
+// the coefficient-major digit array.
+template <typename T, typename D>
+__global__ __launch_bounds__(THREADS) void ks_digits_kernel(const T* __restrict__ big, D* __restrict__ dig, int B,
+                                                            int kN, int tb) {
+    __shared__ uint32_t blk[64][65];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+#pragma unroll
+    for (int m = 0; m < 16; m++) {
+        const int r = w + 4 * m, c = c0 + r, i = i0 + lane;
+        blk[r][lane] = (c < B && i < kN) ? (uint32_t)round_top<T>(big[(size_t)c * (kN + 1) + i], tb) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 16; m++) {
+        const int col = w + 4 * m, c = c0 + lane, i = i0 + col;
+        if (c < B && i < kN) dig[(size_t)i * B + c] = (D)blk[lane][col];
+    }
+}
+
 struct KsPlace {
     int tiles, groups;  // word tiles and ciphertext groups
     int per;            // workgroups per XCD run (the grid is 8 * per)
     int tile_major;     // 1: runs of consecutive tiles, 0: runs of consecutive groups
 };
 
-template <typename T, int V, int WPW, int P>
-__global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict__ big, const T* __restrict__ ksk,
-                                                            T* out, const uint64_t* out_ptrs, int B, int n, int kN,
-                                                            int t, int bb, int ks_row, KsPlace pl) {
+template <typename T, typename D, int V, int WPW, int P>
+__global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict__ big, const D* __restrict__ dig,
+                                                            const T* __restrict__ ksk, T* out,
+                                                            const uint64_t* out_ptrs, int B, int n, int kN, int t,
+                                                            int bb, int ks_row, KsPlace pl) {
     typedef typename Vec16<T>::type vec;
     constexpr int EV = Vec16<T>::N;          // words per 16-byte read
     constexpr int RS = WPW + EV;             // LDS row stride in words (16-byte pad)
@@ -68,13 +99,12 @@ __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict_
     const int w0 = tile * WPW;
     const size_t row = (size_t)ks_row;  // table row stride in words
     const int E = t * V * WPW;               // staged words per coefficient
-    const int tb = t * bb;
     const bool live = c < B;
-    const T* bigc = big + (size_t)(live ? c : 0) * (kN + 1);
+    const D* digc = dig + (live ? c : 0);  // coefficient i's digits at digc[i * B]
 
     T acc[WPW];
 #pragma unroll
-    for (int k = 0; k < WPW; k++) acc[k] = (w0 + k == n && live) ? bigc[kN] : (T)0;
+    for (int k = 0; k < WPW; k++) acc[k] = (w0 + k == n && live) ? big[(size_t)c * (kN + 1) + kN] : (T)0;
 
     // Subtract the rows that coefficient value r selects, from the rows of
     // one coefficient staged at cbuf.
@@ -115,7 +145,7 @@ __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict_
         __syncthreads();
         for (int i = 0; i < kN; i++) {
             if (i + 1 < kN) KS_FETCH(i + 1);
-            const uint32_t r = live ? (uint32_t)round_top<T>(bigc[i], tb) : 0u;
+            const uint32_t r = live ? (uint32_t)digc[(size_t)i * B] : 0u;
             consume(tab + (size_t)(i & 1) * TS, r);
             if (i + 1 < kN) KS_STAGE((i + 1) & 1);
             __syncthreads();
@@ -154,7 +184,7 @@ __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict_
             // not wait for the next group's rows
             uint32_t rr[P];
 #pragma unroll
-            for (int ii = 0; ii < P; ii++) rr[ii] = live ? (uint32_t)round_top<T>(bigc[i0 + ii], tb) : 0u;
+            for (int ii = 0; ii < P; ii++) rr[ii] = live ? (uint32_t)digc[(size_t)(i0 + ii) * B] : 0u;
             if (i0 + P < kN) fetch(i0 + P);
             const T* tbuf = tab + (size_t)(g & 1) * P * TS;
 #pragma unroll
@@ -170,12 +200,15 @@ __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict_
         if (w0 + k <= n) dst[w0 + k] = acc[k];
 }
 
-template <typename T, int V, int WPW, int P>
-int launch_p(tfhe_ctx* c, const T* big, T* out, const uint64_t* out_ptrs, uint32_t B, hipStream_t s) {
+template <typename T, typename D, int V, int WPW, int P>
+int launch_p(tfhe_ctx* c, const T* big, void* dig_ws, T* out, const uint64_t* out_ptrs, uint32_t B, hipStream_t s) {
     const int n = (int)c->p.n, kN = (int)(c->p.k * c->p.N), t = (int)c->p.ks_t, bb = (int)c->p.ks_base_bits;
     constexpr int RS = WPW + Vec16<T>::N;
     const size_t lds = 2ull * P * t * V * RS * sizeof(T);
-    auto k = keyswitch_kernel<T, V, WPW, P>;
+    D* dig = (D*)dig_ws;
+    hipLaunchKernelGGL((ks_digits_kernel<T, D>), dim3((kN + 63) / 64, (B + 63) / 64), dim3(THREADS), 0, s, big, dig,
+                       (int)B, kN, t * bb);
+    auto k = keyswitch_kernel<T, D, V, WPW, P>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return hip_check(c, e, "hipFuncSetAttribute(keyswitch)");
     KsPlace pl;
@@ -184,25 +217,25 @@ int launch_p(tfhe_ctx* c, const T* big, T* out, const uint64_t* out_ptrs, uint32
     pl.per = (pl.tiles * pl.groups + 7) / 8;
     const double table = (double)kN * t * V * (n + 1), inputs = (double)B * (kN + 1);
     pl.tile_major = table > inputs ? 1 : 0;
-    hipLaunchKernelGGL(k, dim3(8 * pl.per), dim3(THREADS), lds, s, big, (const T*)c->d_ksk, out, out_ptrs, (int)B, n,
-                       kN, t, bb, (int)c->ks_row, pl);
+    hipLaunchKernelGGL(k, dim3(8 * pl.per), dim3(THREADS), lds, s, big, (const D*)dig, (const T*)c->d_ksk, out,
+                       out_ptrs, (int)B, n, kN, t, bb, (int)c->ks_row, pl);
     return hip_check(c, hipGetLastError(), "launch keyswitch");
 }
 
 // Coefficients staged per barrier: with 32-bit words the largest of 8, 4, 2
 // whose rows fit the staging registers and that divides kN (fewer barriers
 // for short LWE tiles); with 64-bit words one, which measured faster.
-template <typename T, int V, int WPW>
-int launch_v(tfhe_ctx* c, const T* big, T* out, const uint64_t* out_ptrs, uint32_t B, hipStream_t s) {
+template <typename T, typename D, int V, int WPW>
+int launch_v(tfhe_ctx* c, const T* big, void* dig, T* out, const uint64_t* out_ptrs, uint32_t B, hipStream_t s) {
     const int kN = (int)(c->p.k * c->p.N), t = (int)c->p.ks_t;
     const int E = t * V * WPW;
     if (E > PMAX * THREADS) return ctx_fail(c, TFHE_EINVAL, "key-switching levels exceed the staging tile");
     if constexpr (sizeof(T) == 4) {
-        if (8 * E <= PMAX * THREADS && kN % 8 == 0) return launch_p<T, V, WPW, 8>(c, big, out, out_ptrs, B, s);
-        if (4 * E <= PMAX * THREADS && kN % 4 == 0) return launch_p<T, V, WPW, 4>(c, big, out, out_ptrs, B, s);
-        if (2 * E <= PMAX * THREADS && kN % 2 == 0) return launch_p<T, V, WPW, 2>(c, big, out, out_ptrs, B, s);
+        if (8 * E <= PMAX * THREADS && kN % 8 == 0) return launch_p<T, D, V, WPW, 8>(c, big, dig, out, out_ptrs, B, s);
+        if (4 * E <= PMAX * THREADS && kN % 4 == 0) return launch_p<T, D, V, WPW, 4>(c, big, dig, out, out_ptrs, B, s);
+        if (2 * E <= PMAX * THREADS && kN % 2 == 0) return launch_p<T, D, V, WPW, 2>(c, big, dig, out, out_ptrs, B, s);
     }
-    return launch_p<T, V, WPW, 1>(c, big, out, out_ptrs, B, s);
+    return launch_p<T, D, V, WPW, 1>(c, big, dig, out, out_ptrs, B, s);
 }
 
 // 16 words per lane.  For short LWE (n + 1 <= 128) 8 words per lane would
@@ -210,27 +243,37 @@ int launch_v(tfhe_ctx* c, const T* big, T* out, const uint64_t* out_ptrs, uint32
 // input and redo the digit extraction: at n = 64, 16 words measured 30%
 // faster for 32768 ciphertexts and 3% slower for 4096.
 template <typename T, int V>
-int launch_w(tfhe_ctx* c, const void* big, void* out, const uint64_t* out_ptrs, uint32_t B, hipStream_t s) {
-    return launch_v<T, V, 16>(c, (const T*)big, (T*)out, out_ptrs, B, s);
+int launch_w(tfhe_ctx* c, const void* big, void* dig, void* out, const uint64_t* out_ptrs, uint32_t B,
+             hipStream_t s) {
+    if (c->p.ks_t * c->p.ks_base_bits <= 16)
+        return launch_v<T, uint16_t, V, 16>(c, (const T*)big, dig, (T*)out, out_ptrs, B, s);
+    return launch_v<T, uint32_t, V, 16>(c, (const T*)big, dig, (T*)out, out_ptrs, B, s);
 }
 
 template <typename T>
-int launch_ks_t(tfhe_ctx* c, const void* big, void* out, const uint64_t* out_ptrs, uint32_t B, hipStream_t s) {
+int launch_ks_t(tfhe_ctx* c, const void* big, void* dig, void* out, const uint64_t* out_ptrs, uint32_t B,
+                hipStream_t s) {
     switch (c->p.ks_base_bits) {
-        case 1: return launch_w<T, 2>(c, big, out, out_ptrs, B, s);
-        case 2: return launch_w<T, 4>(c, big, out, out_ptrs, B, s);
-        case 3: return launch_w<T, 8>(c, big, out, out_ptrs, B, s);
-        case 4: return launch_w<T, 16>(c, big, out, out_ptrs, B, s);
+        case 1: return launch_w<T, 2>(c, big, dig, out, out_ptrs, B, s);
+        case 2: return launch_w<T, 4>(c, big, dig, out, out_ptrs, B, s);
+        case 3: return launch_w<T, 8>(c, big, dig, out, out_ptrs, B, s);
+        case 4: return launch_w<T, 16>(c, big, dig, out, out_ptrs, B, s);
         default: return ctx_fail(c, TFHE_EINVAL, "key-switching base must be 2^1..2^4");
     }
 }
 
 }  // namespace
 
-int launch_keyswitch(tfhe_ctx* c, const void* big_in, void* out, const uint64_t* out_ptrs, uint32_t B,
-                     hipStream_t s) {
+size_t ks_digits_bytes(const tfhe_ctx* c, uint32_t B) {
+    const size_t d = c->p.ks_t * c->p.ks_base_bits <= 16 ? 2 : 4;
+    return ((size_t)B * c->p.k * c->p.N * d + 255) & ~(size_t)255;
+}
+
+int launch_keyswitch(tfhe_ctx* c, const void* big_in, void* out, const uint64_t* out_ptrs, uint32_t B, void* dig,
+                     size_t dig_cap, hipStream_t s) {
     if (B == 0) return TFHE_OK;
+    if (!dig || dig_cap < ks_digits_bytes(c, B)) return ctx_fail(c, TFHE_EINVAL, "key-switch digit buffer too small");
     TimedLaunch tl(c, s, 1, B);
-    return c->q == 32 ? launch_ks_t<uint32_t>(c, big_in, out, out_ptrs, B, s)
-                      : launch_ks_t<uint64_t>(c, big_in, out, out_ptrs, B, s);
+    return c->q == 32 ? launch_ks_t<uint32_t>(c, big_in, dig, out, out_ptrs, B, s)
+                      : launch_ks_t<uint64_t>(c, big_in, dig, out, out_ptrs, B, s);
 }

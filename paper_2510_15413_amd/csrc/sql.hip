@@ -148,8 +148,10 @@ struct Exec {
         const size_t ptr_b = al((size_t)chunk * 8);
         const size_t tvi_b = al((size_t)chunk * 4);
         // pieces of a level can be smaller than the chunk (and then take the
-        // multi-workgroup blind rotation), so size for any batch up to it
-        const size_t br_b = al(blind_rotate_ws_bytes_upto(c, chunk));
+        // multi-workgroup blind rotation), so size for any batch up to it;
+        // the key switch's digits reuse the region once the blind rotation
+        // that precedes it in the stream has finished with it
+        const size_t br_b = std::max(al(blind_rotate_ws_bytes_upto(c, chunk)), al(ks_digits_bytes(c, chunk)));
         const size_t seg_b = al(flat.size() * sizeof(Segment));
         const size_t st_b = al(starts.size() * 4);
         const size_t total = tmp_b + lwe_b + big_b + ptr_b + tvi_b + br_b + seg_b + st_b;
@@ -197,7 +199,7 @@ struct Exec {
                 if ((e = launch_blind_rotate(c, lwe, net.lut_table, net.lut_table ? tvi : nullptr, big, pc.total,
                                              brws, br_b, rs)))
                     break;
-                if ((e = launch_keyswitch(c, big, nullptr, ptrs, pc.total, rs))) break;
+                if ((e = launch_keyswitch(c, big, nullptr, ptrs, pc.total, brws, br_b, rs))) break;
             }
             return e;
         };
@@ -431,7 +433,8 @@ extern "C" int sql_server_create(tfhe_ctx* c, size_t budget, uint32_t max_batch,
                         (size_t)c->p.n * 2 * c->p.l * 2 * NL * 2 * c->p.N;
     const size_t lwe_b = al256((size_t)max_batch * lw * wb), big_b = al256((size_t)max_batch * bw * wb);
     const size_t ptr_b = al256((size_t)max_batch * 8), tvi_b = al256((size_t)max_batch * 4);
-    const size_t br_b = al256(blind_rotate_ws_bytes_upto(c, max_batch));
+    // blind-rotation workspace, reused by the key switch's digits
+    const size_t br_b = std::max(al256(blind_rotate_ws_bytes_upto(c, max_batch)), al256(ks_digits_bytes(c, max_batch)));
     const size_t seg_b = al256(cap * sizeof(Segment)), st_b = al256(cap * 4);
     const size_t set_b = lwe_b + big_b + ptr_b + tvi_b + br_b + seg_b + st_b;
     sv->book.fixed = keys + 2 * set_b;
@@ -602,7 +605,7 @@ extern "C" int sql_server_step(sql_server* sv, void* stream, uint32_t* gates, ui
         if (t.total) {
             if ((rc = launch_combine(c, S.dsegs, S.dstart, (int)nseg, t.total, S.lwe, S.ptrs, S.tvi, s)) ||
                 (rc = launch_blind_rotate(c, S.lwe, nullptr, nullptr, S.big, t.total, S.brws, sv->brws_bytes, s)) ||
-                (rc = launch_keyswitch(c, S.big, nullptr, S.ptrs, t.total, s)))
+                (rc = launch_keyswitch(c, S.big, nullptr, S.ptrs, t.total, S.brws, sv->brws_bytes, s)))
                 return rc;
         }
         if ((rc = hip_check(c, hipEventRecord(S.ev, s), "server tick event"))) return rc;
