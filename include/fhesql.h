@@ -120,14 +120,23 @@ int tfhe_set_kernel(tfhe_ctx* ctx, int kind);
 #define TFHE_TUNE_MAX_BATCH 1
 #define TFHE_TUNE_ROW_PASS 2
 /*   TFHE_TUNE_DIGIT_BLOCKS 0 = the best digit grouping that fits in LDS
- *                        (default): with one MFMA row pass, one component's
+ *                        (default): with one MFMA row pass, when both
+ *                        accumulator components fit in LDS (small N),
+ *                        l <= 4 and the batch loses no occupancy by it (at
+ *                        N = 256: up to 16 ciphertexts per CU), all key and
+ *                        digit blocks of a CMux step staged together (three
+ *                        barriers per step, the second component's digits
+ *                        formed while the first component's blocks run);
+ *                        else one component's
  *                        blocks at a time with accumulator component 0 held
  *                        in LDS; else all blocks of a CMux step at once, else
  *                        pairs of levels of one component (l even), else one
  *                        (u,p) block at a time; 1 = one block at a time;
  *                        2 = pairs when l is even and they fit, else one;
  *                        3 = all blocks of a step, accumulator in global
- *                        memory, when they fit.
+ *                        memory, when they fit; 4 = one component's blocks
+ *                        at a time with component 0 in LDS, when it fits.
+ *                        Every grouping gives the same output bits.
  * The blind-rotation workspace depends on the row pass and digit grouping
  * (several passes with per-group digits add a digit cache).  Direct calls and
  * the level executor size it per call; a server sizes it at creation, and a

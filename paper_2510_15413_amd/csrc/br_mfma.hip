@@ -78,7 +78,9 @@ FHE_DEV size_t acc_idx(int N, int v, int j, int c) {
 // workgroups).
 // With acopy the item's own accumulator words are also copied there (same
 // layout), which seeds the next accumulator of the multi-workgroup path.
-template <typename T, int R, int U, bool GC = false, int DS = 1, bool AC = false>
+// TH: threads that share the work (the first TH of the workgroup, or with
+// TH = THREADS / 2 either half, each half forming its own slice).
+template <typename T, int R, int U, bool GC = false, int DS = 1, bool AC = false, int TH = THREADS>
 FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u_lo, int p_lo, int p_n, int l,
                           int bgb, int8_t* gdst = nullptr, int ds = 0, T* acopy = nullptr) {
     typedef T vec4 __attribute__((ext_vector_type(4)));
@@ -86,8 +88,9 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
     constexpr int NG = N / 4;  // 4-word groups per component
     constexpr int ITEMS = CTS * U * NG / DS;
     static_assert((CTS * U * NG) % (DS * CTS) == 0, "digit slices must hold whole groups of 16 items");
+    static_assert(THREADS % TH == 0 && TH % CTS == 0, "thread subsets must hold whole ciphertext groups");
     const int it0 = ds * ITEMS;
-    constexpr int IPT = (ITEMS + THREADS - 1) / THREADS;
+    constexpr int IPT = (ITEMS + TH - 1) / TH;
     constexpr int G = IPT < 4 ? IPT : 4;
     constexpr int Q = Torus<T>::Q;
     // Level p of the balanced decomposition of x is field p of
@@ -107,9 +110,9 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
     // the item addresses below do not change from step to step; an opaque
     // thread index keeps them from being hoisted out of the caller's step
     // loop (held there they would crowd out the MFMA phase's registers)
-    int tix = threadIdx.x;
+    int tix = TH == THREADS ? (int)threadIdx.x : (int)(threadIdx.x & (TH - 1));
     __asm__ volatile("" : "+v"(tix));
-    const int c = tix & (CTS - 1);  // fixed per thread (THREADS % 16 == 0); ab is its abar_i
+    const int c = tix & (CTS - 1);  // fixed per thread (TH % 16 == 0); ab is its abar_i
     const int neg = ab >= N;
     const int es = neg ? ab - N : ab;
     // coefficient 4kg+e reads rotated index 4kg+e-es: group kg-qs (+1), word e+sh
@@ -120,17 +123,17 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
     const bool hi1 = sh == 3, hi2 = s2, hi3 = sh != 0;
     // all ones when the rotation exponent is at least N (X^N = -1)
     const T negm = neg ? ~(T)0 : (T)0;
-    // item it = tix + k*THREADS covers group (it0 + it) >> 4 of the U
+    // item it = tix + k*TH covers group (it0 + it) >> 4 of the U
     // components (all unsigned, so that the divisions are shifts)
     const unsigned rest0 = ((unsigned)it0 + (unsigned)tix) >> 4;
-    constexpr unsigned RSTEP = THREADS / CTS;
+    constexpr unsigned RSTEP = TH / CTS;
     const vec4* Pc = (const vec4*)src + c;
     for (int k0 = 0; k0 < IPT; k0 += G) {
         vec4 dv[G], r0[G], r1[G];
         int kq[G];
 #pragma unroll
         for (int k = 0; k < G; k++) {
-            if (ITEMS % THREADS != 0 && (unsigned)tix + (unsigned)(k0 + k) * THREADS >= (unsigned)ITEMS) continue;
+            if (ITEMS % TH != 0 && (unsigned)tix + (unsigned)(k0 + k) * TH >= (unsigned)ITEMS) continue;
             const unsigned rest = rest0 + (unsigned)(k0 + k) * RSTEP;
             const unsigned kg = rest & (NG - 1);
             const unsigned ub = (U == 1 ? 0u : rest / NG) + (unsigned)u_lo;
@@ -144,7 +147,7 @@ FHE_DEV void digits_phase(const T* __restrict__ src, int ab, int8_t* dbuf, int u
         }
 #pragma unroll
         for (int k = 0; k < G; k++) {
-            if (ITEMS % THREADS != 0 && (unsigned)tix + (unsigned)(k0 + k) * THREADS >= (unsigned)ITEMS) continue;
+            if (ITEMS % TH != 0 && (unsigned)tix + (unsigned)(k0 + k) * TH >= (unsigned)ITEMS) continue;
             const unsigned rest = rest0 + (unsigned)(k0 + k) * RSTEP;
             const int kg = (int)(rest & (NG - 1));
             const int u = (U == 1 ? 0 : (int)(rest / NG)) + u_lo;
@@ -221,6 +224,69 @@ FHE_DEV v4i afrag_combine(const ARaw& r, int sh) {
     a[2] = (int)__builtin_amdgcn_alignbyte(r.w[3], r.w[2], sh);
     a[3] = (int)__builtin_amdgcn_alignbyte(r.w[4], r.w[3], sh);
     return a;
+}
+
+// Small rings (N <= 256, 32-bit words, the step-keyed schedule): a limb's diagonal
+// iteration is only RP <= 4 MFMAs, shorter than an LDS read, so the limbs
+// are unrolled and each fragment of limb m+1 is requested as soon as
+// limb m's iteration that uses it has issued its MFMAs (every diagonal
+// fragment serves one iteration), a limb ahead of its use, leaving no LDS
+// wait inside a limb and holding one set of 2RP-1 fragments.
+template <typename T, int R, int KC>
+FHE_DEV void mfma_block_small(const uint8_t* kslot, const int8_t* dblk, int v, int jr, T (&delta)[R][4]) {
+    constexpr int N = R * 64;
+    constexpr int NL = Torus<T>::LIMBS;
+    constexpr int CP = R;
+    constexpr int NF = 2 * CP - 1;                                 // diagonals -(CP-1) .. CP-1
+    constexpr int KCS = 2 * NL * 2 * N + KCOPY_PAD;                // copy stride
+    static_assert(KC == 4 && NL == 4, "small-ring block: four shifted key copies, 32-bit words");
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int sh0 = ((N - 1) - 16 * jr - r + 16 * g) & 3;
+    // fragment k (diagonal k - (CP-1)) of limb m at byte 2N m + 64 k of this
+    // lane's copy past the base, which is moved down by 64 (CP-1) so that
+    // every offset is a positive immediate (it stays inside LDS: the key
+    // slot follows the digit buffer)
+    int sbo = (N - 1) - 16 * jr - r + 16 * g - sh0 - 64 * (CP - 1);
+    __asm__ volatile("" : "+v"(sbo));
+    const uint8_t* S0 = kslot + (size_t)sh0 * KCS + (size_t)v * NL * (2 * N) + sbo;
+    v4i bf[CP];
+#pragma unroll
+    for (int cc = 0; cc < CP; cc++) bf[cc] = *(const v4i*)(dblk + (size_t)cc * 1024 + lane * 16);
+    ARaw F[NF];
+#pragma unroll
+    for (int k = 0; k < NF; k++) F[k] = afrag_raw<4>(S0 + 64 * k);
+#pragma unroll
+    for (int m = 0; m < NL; m++) {
+        if (m == 0) __builtin_amdgcn_s_setprio(3);
+        else if (m == 1) __builtin_amdgcn_s_setprio(2);
+        else if (m == 2) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
+        v4i acc[CP];
+#pragma unroll
+        for (int s = 0; s < CP; s++) {
+            // iteration s: MFMA (a, c = (a+s) mod CP) on diagonal c - a, which
+            // is s (fragment s + CP - 1) or s - CP (fragment s - 1)
+#pragma unroll
+            for (int a = 0; a < CP; a++) {
+                const int k = a + s < CP ? s + CP - 1 : s - 1;
+                const v4i A = afrag_combine<4>(F[k], 0);
+                acc[a] = s == 0 ? __builtin_amdgcn_mfma_i32_16x16x64_i8(A, bf[(a + s) % CP], v4i{0, 0, 0, 0}, 0, 0, 0)
+                                : __builtin_amdgcn_mfma_i32_16x16x64_i8(A, bf[(a + s) % CP], acc[a], 0, 0, 0);
+            }
+            if (m + 1 < NL) {
+                const uint8_t* Sn = S0 + (size_t)(m + 1) * (2 * N);
+                F[s + CP - 1] = afrag_raw<4>(Sn + 64 * (s + CP - 1));
+                if (s > 0) F[s - 1] = afrag_raw<4>(Sn + 64 * (s - 1));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int a = 0; a < CP; a++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) delta[a][e] += (T)((T)(int64_t)acc[a][e] << (8 * m));
+    }
+    __builtin_amdgcn_s_setprio(0);
 }
 
 // One (u,p) key block for this wave: all limbs, the pass's RP row tiles.
@@ -328,8 +394,9 @@ FHE_DEV void mfma_block(const uint8_t* kslot, const int8_t* dblk, int v, int jr,
 // DG: digit blocks formed per rotate-diff pass -- 0 all (k+1)l blocks of a
 // step up front (key double-buffered), -1 the l blocks of one component
 // before that component's MFMA blocks with accumulator component 0 held in
-// LDS (key double-buffered), else DG consecutive levels of one component just
-// before their MFMA blocks.
+// LDS (key double-buffered), -2 (both components in LDS, small N) the
+// step-keyed schedule described at its loop, else DG consecutive levels of
+// one component just before their MFMA blocks.
 template <typename T, int R, int RP, int DG>
 __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void br_mfma_kernel(BrArgs a) {
     constexpr int N = R * 64;
@@ -340,12 +407,14 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     constexpr int KCS = KSLOT + (KC == 4 ? KCOPY_PAD : 0);  // copy stride
     constexpr int LG = __builtin_ctz(2 * N);
     constexpr bool ACCL = DG < 0;
+    constexpr bool SK = DG == -2;    // all key blocks of a step staged together
     constexpr bool DALL = DG <= 0;   // a step's digits formed before its blocks run
-    constexpr bool DOUBLE = DALL;
+    constexpr bool DOUBLE = DALL && !SK;
     constexpr int NPASS = R / RP;
     static_assert(!ACCL || NPASS == 1, "LDS accumulator mode needs one row pass");
     // small N: accumulator component 1 in LDS as well (right after component 0)
     constexpr bool ACC1L = ACCL && 2 * N * CTS * (int)sizeof(T) <= 65536;
+    static_assert(!SK || ACC1L, "the step-keyed schedule keeps both components in LDS");
     // Several row passes with digits formed per group: the first pass also
     // writes each group's digits to a per-workgroup global cache (L2
     // resident) and the later passes of the step copy them back to LDS.
@@ -359,9 +428,9 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
 
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     int8_t* dbuf = (int8_t*)smem;
-    size_t off = (size_t)(ACCL ? l : DALL ? NB : DG) * R * 1024;
+    size_t off = (size_t)(SK ? NB : ACCL ? l : DALL ? NB : DG) * R * 1024;
     uint8_t* kbuf = smem + off;
-    off += (size_t)(DOUBLE ? 2 : 1) * KC * KCS;
+    off += (size_t)(SK ? NB : DOUBLE ? 2 : 1) * KC * KCS;
     T* acc0 = (T*)(smem + off);  // ACCL: accumulator component 0, [N/4][16 cts][4]
 
     // With all digits of a step formed before its blocks (DALL) the
@@ -433,6 +502,48 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
         KEY_LOAD(kbase);
         KEY_STORE(kbuf);
     }
+    // SK: the l key blocks of one component (half h of a step), staged
+    // through registers, thread idx taking uint4 idx of the half (up to l = 4)
+    constexpr int KVH = SK ? (4 * KU + THREADS - 1) / THREADS : 1;
+    uint4 hk[KVH];
+    uint32_t hn[KVH];  // KC = 4: the word after each uint4 (0 at a block's end)
+    auto key_load_half = [&](int step, int h) {
+        const uint4* ks = kbase + ((size_t)step * NB + (size_t)h * l) * KU;
+#pragma unroll
+        for (int q = 0; q < KVH; q++) {
+            const int idx = tid + q * THREADS;
+            if (idx < l * KU) {
+                hk[q] = ks[idx];
+                if (KC == 4) hn[q] = (idx % KU) + 1 < KU ? *(const uint32_t*)(ks + idx + 1) : 0u;
+            }
+        }
+    };
+    auto key_store_half = [&](int h) {
+#pragma unroll
+        for (int q = 0; q < KVH; q++) {
+            const int idx = tid + q * THREADS;
+            if (idx < l * KU) {
+                const int w = idx % KU;
+                uint4* kd = (uint4*)(kbuf + (size_t)(h * l + idx / KU) * KC * KCS);
+                kd[w] = hk[q];
+                if (KC == 4) {
+                    const uint4 x = hk[q];
+#pragma unroll
+                    for (int j = 1; j < 4; j++)
+                        kd[j * (KCS / 16) + w] = make_uint4(__builtin_amdgcn_alignbyte(x.y, x.x, j),
+                                                            __builtin_amdgcn_alignbyte(x.z, x.y, j),
+                                                            __builtin_amdgcn_alignbyte(x.w, x.z, j),
+                                                            __builtin_amdgcn_alignbyte(hn[q], x.w, j));
+                }
+            }
+        }
+    };
+    if constexpr (SK) {
+        key_load_half(0, 0);
+        key_store_half(0);
+        key_load_half(0, 1);
+        key_store_half(1);
+    }
     __syncthreads();
 
     T* src = ws0;
@@ -468,7 +579,54 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
         if (rows_lds) get(acc0);
         else get(ws0);
     }
-    for (int i = 0; i < n; i++) {
+    // Step-keyed schedule (SK): three barriers per step.  The digits of
+    // component 0 are formed first; the digits of component 1 are formed
+    // while component 0's blocks run (the v = 0 waves before their blocks,
+    // the v = 1 waves after theirs, so that on each SIMD one wave's digit
+    // work meets the other's MFMAs), into their own l blocks of the digit
+    // buffer.  The key area holds all 2l blocks of a step; the next step's
+    // component-0 half is stored once this step's component-0 blocks are
+    // done (after the second barrier), its component-1 half at the start of
+    // the next step (its blocks start after that step's second barrier).
+    if constexpr (SK) {
+        int8_t* dbuf1 = dbuf + (size_t)l * R * 1024;
+        auto block = [&](int ub) {
+            const uint8_t* ks = kbuf + (size_t)ub * KC * KCS;
+            const int8_t* db = dbuf + (size_t)ub * R * 1024;
+            if constexpr (KC == 4 && NL == 4) mfma_block_small<T, R, KC>(ks, db, v, jr, accr);
+            else mfma_block<T, R, RP, KC>(ks, db, v, jr, 0, accr);
+        };
+        for (int i = 0; i < n; i++) {
+            const int ab = cd_live ? (int)mod_switch<T>(a_next, LG) : 0;
+            if (i + 1 < n) a_next = lwe_cd[i + 1];
+            if (i > 0) key_store_half(1);
+            digits_phase<T, R, 1>(acc0, ab, dbuf, 0, 0, l, l, a.bg_bits);
+            if (i + 1 < n) key_load_half(i + 1, 0);
+            __syncthreads();
+            if (v == 0) digits_phase<T, R, 1, false, 2, false, THREADS / 2>(acc1, ab, dbuf1, 0, 0, l, l, a.bg_bits,
+                                                                            nullptr, 0);
+            for (int ub = 0; ub < l; ub++) block(ub);
+            if (v == 1) digits_phase<T, R, 1, false, 2, false, THREADS / 2>(acc1, ab, dbuf1, 0, 0, l, l, a.bg_bits,
+                                                                            nullptr, 1);
+            __syncthreads();
+            if (i + 1 < n) {
+                key_store_half(0);
+                key_load_half(i + 1, 1);
+            }
+            for (int ub = l; ub < NB; ub++) block(ub);
+            uint32_t ro = (uint32_t)rbase;
+            __asm__ volatile("" : "+v"(ro));
+#pragma unroll
+            for (int q = 0; q < RP; q++) {
+                vec4 o;
+#pragma unroll
+                for (int e = 0; e < 4; e++) o[e] = accr[q][e];
+                *(vec4*)(acc0 + ro + q * STEP4) = o;
+            }
+            __syncthreads();
+        }
+    }
+    if constexpr (!SK) for (int i = 0; i < n; i++) {
         const int ab = cd_live ? (int)mod_switch<T>(a_next, LG) : 0;
         if (i + 1 < n) a_next = lwe_cd[i + 1];
         if (DALL && !ACCL) {
@@ -833,11 +991,13 @@ int launch_t(tfhe_ctx* c, const BrArgs& a, size_t lds, hipStream_t s) {
 }
 
 // LDS bytes of the kernel with digit group dg (0 = all blocks of a step,
-// -1 = one component's blocks plus accumulator component 0).
+// -1 = one component's blocks plus accumulator component 0, -2 = all digit
+// and key blocks of a step plus both accumulator components).
 size_t lds_need(const tfhe_ctx* c, int dg) {
     const int N = c->p.N, l = c->p.l;
     const int NL = c->q == 32 ? 4 : 8;
     const size_t kslot = N <= 256 ? 4 * (2ull * NL * 2 * N + KCOPY_PAD) : 2ull * NL * 2 * N;
+    if (dg == -2) return 2ull * l * (N / 64) * 1024 + 2ull * l * kslot + 2ull * N * CTS * word_bytes(c);
     size_t b = (size_t)(dg < 0 ? l : dg == 0 ? 2 * l : dg) * (N / 64) * 1024;
     b += (dg <= 0 ? 2 : 1) * kslot;
     if (dg < 0) b += (size_t)N * CTS * word_bytes(c) * (2ull * N * CTS * word_bytes(c) <= 65536 ? 2 : 1);
@@ -869,13 +1029,27 @@ int plan_rp(const tfhe_ctx* c) {
 
 // Largest digit grouping that fits LDS and the digit_blocks knob (0 auto,
 // 1 one block, 2 pairs of levels when l is even, 3 all blocks of a step with
-// the accumulator in global memory).  Auto prefers, with one row pass, the
-// per-component grouping that keeps accumulator component 0 in LDS.
-int plan_dg(const tfhe_ctx* c, int R, int rp) {
+// the accumulator in global memory, 4 one component's blocks with
+// accumulator component 0 in LDS).  Auto prefers, with one row pass, the
+// step-keyed schedule when both accumulator components fit in LDS (small N,
+// l <= 4) and it costs no occupancy for a batch of B, else the
+// per-component grouping that keeps component 0 in LDS.
+int plan_dg(const tfhe_ctx* c, int R, int rp, uint32_t B) {
     const size_t max_lds = (size_t)c->prop.maxSharedMemoryPerMultiProcessor > 0
                                ? (size_t)c->prop.maxSharedMemoryPerMultiProcessor
                                : (size_t)160 * 1024;
-    if (rp == R && c->digit_blocks == 0 && lds_need(c, -1) <= max_lds) return -1;
+    const bool both_lds = 2ull * c->p.N * CTS * word_bytes(c) <= 65536;
+    if (rp == R && c->digit_blocks == 0 && both_lds && c->p.l <= 4 && lds_need(c, -2) <= max_lds) {
+        // The step-keyed schedule stages a whole step's keys, which can leave
+        // room for fewer workgroups per CU than the per-component one (at
+        // N = 256: one instead of two): take it when it keeps two per CU, or
+        // when the batch's groups all fit at its occupancy.
+        const int cus = c->prop.multiProcessorCount > 0 ? c->prop.multiProcessorCount : 256;
+        const uint64_t groups = ((uint64_t)B + CTS - 1) / CTS;
+        const size_t per_cu = max_lds / lds_need(c, -2);
+        if (per_cu >= 2 || lds_need(c, -1) > max_lds / 2 || groups <= (uint64_t)cus * per_cu) return -2;
+    }
+    if (rp == R && (c->digit_blocks == 0 || c->digit_blocks == 4) && lds_need(c, -1) <= max_lds) return -1;
     if ((c->digit_blocks == 0 || c->digit_blocks == 3) && lds_need(c, 0) <= max_lds) return 0;
     if (c->digit_blocks != 1 && c->p.l % 2 == 0 && lds_need(c, 2) <= max_lds) return 2;
     if (lds_need(c, 1) > max_lds) return kNoFit;
@@ -886,6 +1060,9 @@ template <typename T, int R, int RP>
 int dispatch_dg(tfhe_ctx* c, const BrArgs& a, int dg, hipStream_t s) {
     if constexpr (RP == R) {
         if (dg == -1) return launch_t<T, R, RP, -1>(c, a, lds_need(c, -1), s);
+    }
+    if constexpr (RP == R && 2 * R * 64 * CTS * sizeof(T) <= 65536) {
+        if (dg == -2) return launch_t<T, R, RP, -2>(c, a, lds_need(c, -2), s);
     }
     if (dg == 0) return launch_t<T, R, RP, 0>(c, a, lds_need(c, 0), s);
     if (dg == 2) return launch_t<T, R, RP, 2>(c, a, lds_need(c, 2), s);
@@ -901,7 +1078,7 @@ int dispatch_dg(tfhe_ctx* c, const BrArgs& a, int dg, hipStream_t s) {
 size_t acc_ws_bytes(const tfhe_ctx* c, uint32_t B) {
     const int R = (int)c->p.N / 64, rp = plan_rp(c);
     if (rp <= 0) return 0;
-    const int dg = plan_dg(c, R, rp);
+    const int dg = plan_dg(c, R, rp, B);
     if (dg == kNoFit) return 0;
     const size_t grid = (B + CTS - 1) / CTS;
     const size_t comp = (size_t)c->p.N * CTS * word_bytes(c);  // one component of a workgroup
@@ -945,7 +1122,7 @@ size_t split_ws_bytes(const tfhe_ctx* c, uint32_t B) {
 
 size_t dcache_bytes(const tfhe_ctx* c, uint32_t B) {
     const int R = (int)c->p.N / 64, rp = plan_rp(c);
-    if (rp <= 0 || R / rp <= 1 || plan_dg(c, R, rp) <= 0) return 0;
+    if (rp <= 0 || R / rp <= 1 || plan_dg(c, R, rp, B) <= 0) return 0;
     const size_t grid = (B + CTS - 1) / CTS;
     return grid * 2 * (size_t)c->p.l * R * 1024;
 }
@@ -994,7 +1171,7 @@ int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_
     const int N = (int)c->p.N;
     const int rp = plan_rp(c);
     if (N < 64 || rp <= 0) return ctx_fail(c, TFHE_EINVAL, "unsupported N for the MFMA kernel");
-    const int dg = plan_dg(c, N / 64, rp);
+    const int dg = plan_dg(c, N / 64, rp, B);
     if (dg == kNoFit) return ctx_fail(c, TFHE_EINVAL, "parameters exceed LDS capacity of the MFMA kernel");
     // the tuning may have changed since the workspace was sized
     const size_t need = mfma_ws_bytes(c, B);

@@ -282,7 +282,7 @@ extern "C" int tfhe_set_tuning(tfhe_ctx* c, int key, int64_t value) {
         return TFHE_OK;
     }
     if (key == TFHE_TUNE_DIGIT_BLOCKS) {
-        if (value < 0 || value > 3) return ctx_fail(c, TFHE_EINVAL, "digit blocks must be 0, 1, 2 or 3");
+        if (value < 0 || value > 4) return ctx_fail(c, TFHE_EINVAL, "digit blocks must be 0, 1, 2, 3 or 4");
         c->digit_blocks = (int)value;
         return TFHE_OK;
     }

@@ -58,14 +58,16 @@ def value(bl):
     return sum(int(b) << (4 * i) for i, b in enumerate(bl))
 
 
-@pytest.mark.parametrize("digit_blocks", [0, 1, 2, 3])
-@pytest.mark.parametrize("pname", ["toy", "tiny64"])
+@pytest.mark.parametrize("digit_blocks", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("pname", ["toy", "tiny", "tiny64"])
 def test_bootstrap_per_block_digit_path(pname, digit_blocks):
-    """Every digit grouping gives the oracle's bits: one component's blocks with
-    accumulator component 0 in LDS (the default with one row pass), one (u,p)
-    block at a time, two levels of a component at a time (the 2048-coefficient
-    64-bit set's grouping), and all blocks of a step with the accumulator in
-    global memory."""
+    """Every digit grouping gives the oracle's bits: the step-keyed schedule
+    with both accumulator components in LDS (the default at N <= 512 with
+    32-bit words), one component's blocks with accumulator component 0 in LDS
+    (the default with one row pass otherwise, forced by 4), one (u,p) block at
+    a time, two levels of a component at a time (the 2048-coefficient 64-bit
+    set's grouping), and all blocks of a step with the accumulator in global
+    memory."""
     p = si.PARAMS[pname]
     K, ctx = keys(pname)
     ctx.set_tuning(digit_blocks=digit_blocks)
