@@ -99,8 +99,12 @@ size_t tfhe_ksk_words(const tfhe_params* p);
  * pointers otherwise -- keys generated on the device need no host round trip;
  * sizes in bytes must match tfhe_bsk_words/tfhe_ksk_words), builds the
  * device-only limb-planar Toeplitz form of the BSK and allocates workspace
- * lazily.  Blocks until the keys are on the device.  The context owns its
- * copies; the caller keeps ownership of bsk/ksk. */
+ * lazily.  With torus_bits = 32 and N = 1024 it also builds, when the device
+ * has room, the BSK's 16-byte key windows (16 bytes per byte of the limb
+ * form: 968 MB at n = 630, l = 3), from which the blind rotation reads its
+ * A fragments directly; without room it stages the key in LDS instead (same
+ * output bits).  Blocks until the keys are on the device.  The context owns
+ * its copies; the caller keeps ownership of bsk/ksk. */
 int tfhe_ctx_create(const tfhe_params* p, const void* bsk, size_t bsk_bytes,
                     const void* ksk, size_t ksk_bytes, int keys_on_device,
                     tfhe_ctx** out);
@@ -135,7 +139,13 @@ int tfhe_set_kernel(tfhe_ctx* ctx, int kind);
  *                        2 = pairs when l is even and they fit, else one;
  *                        3 = all blocks of a step, accumulator in global
  *                        memory, when they fit; 4 = one component's blocks
- *                        at a time with component 0 in LDS, when it fits.
+ *                        at a time with component 0 in LDS and the key
+ *                        staged in LDS, when it fits.  With the key windows
+ *                        of a 1024-coefficient 32-bit context (see
+ *                        tfhe_ctx_create) and one row pass, 0 reads the key
+ *                        from them instead (no key staging, the second
+ *                        component's digits formed while the first
+ *                        component's blocks run).
  *                        Every grouping gives the same output bits.
  * The blind-rotation workspace depends on the row pass and digit grouping
  * (several passes with per-group digits add a digit cache).  Direct calls and

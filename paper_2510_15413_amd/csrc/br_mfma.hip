@@ -50,6 +50,7 @@ constexpr int KCOPY_PAD = 96;
 struct BrArgs {
     const void* lwe;          // [B][n+1] words
     const int8_t* bsk8;       // [n][2l][2][LIMBS][2N]
+    const uint4* win;         // [n][2l][2][LIMBS][2N] 16-byte key windows, or null
     const void* tv;           // test polynomials [ntv][N] words
     const int32_t* tv_index;  // [B] or null
     void* out;                // [B][N+1] words
@@ -289,6 +290,63 @@ FHE_DEV void mfma_block_small(const uint8_t* kslot, const int8_t* dblk, int v, i
     __builtin_amdgcn_s_setprio(0);
 }
 
+// Windowed key (N = 1024, 32-bit words, one row pass): every A fragment is
+// one 16-byte-aligned global load.  The window array holds, for every limb
+// of every key polynomial and every byte offset x of its reversed extended
+// byte array S, the 16 bytes S[x .. x+15] at 16-byte slot x, so lane (r, g)
+// of a wave finds its fragment of diagonal d at slot x0 + 64 d and the 64
+// lanes of a wave read one contiguous kilobyte.  No key is staged in LDS,
+// no byte alignment is done, and consecutive blocks need no barrier.  The
+// fragments of iteration t (limb t / CP, diagonal pair t % CP) are requested
+// two iterations ahead through a ring of 4 register slots, carried across
+// blocks by the caller (wnext is the block that runs next, whose first two
+// iterations the last ones request).
+template <typename T, int R>
+FHE_DEV void mfma_block_wk(const uint4* __restrict__ wblk, const uint4* __restrict__ wnext, const int8_t* dblk,
+                           int v, int jr, T (&delta)[R][4], v4i (&F0)[4], v4i (&F1)[4]) {
+    constexpr int N = R * 64;
+    constexpr int NL = Torus<T>::LIMBS;
+    constexpr int CP = R;
+    constexpr int IT = NL * CP;  // iterations per block
+    static_assert(CP == 16 && NL == 4, "windowed key: 16 chunks, four limbs");
+    const int lane = threadIdx.x & 63;
+    v4i bf[CP];
+#pragma unroll
+    for (int cc = 0; cc < CP; cc++) bf[cc] = *(const v4i*)(dblk + (size_t)cc * 1024 + lane * 16);
+#pragma unroll
+    for (int m = 0; m < NL; m++) {
+        if (m == 0) __builtin_amdgcn_s_setprio(3);
+        else if (m == 1) __builtin_amdgcn_s_setprio(2);
+        else if (m == 2) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
+        v4i acc[CP];
+#pragma unroll
+        for (int s = 0; s < CP; s++) {
+            const int t = m * CP + s;
+            {
+                // request iteration t + 2 (of the next block past the end)
+                const int tn = (t + 2) % IT;
+                const uint4* b = (t + 2 < IT ? wblk : wnext) + (size_t)(tn / CP) * (2 * N);
+                const int sn = tn % CP;
+                F0[(t + 2) & 3] = __builtin_bit_cast(v4i, b[64 * sn]);
+                if (sn > 0) F1[(t + 2) & 3] = __builtin_bit_cast(v4i, b[64 * (sn - CP)]);
+            }
+#pragma unroll
+            for (int a = 0; a < CP; a++) {
+                const v4i A = a + s < CP ? F0[t & 3] : F1[t & 3];
+                acc[a] = s == 0 ? __builtin_amdgcn_mfma_i32_16x16x64_i8(A, bf[(a + s) % CP], v4i{0, 0, 0, 0}, 0, 0, 0)
+                                : __builtin_amdgcn_mfma_i32_16x16x64_i8(A, bf[(a + s) % CP], acc[a], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int a = 0; a < CP; a++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) delta[a][e] += (T)((T)(int64_t)acc[a][e] << (8 * m));
+    }
+    __builtin_amdgcn_s_setprio(0);
+}
+
 // One (u,p) key block for this wave: all limbs, the pass's RP row tiles.
 // KC = 4: the slot holds four copies of the key bytes, copy j shifted down by
 // j bytes, so a lane reads its 16 bytes as 4 aligned words of copy (b & 3).
@@ -408,8 +466,9 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
     constexpr int LG = __builtin_ctz(2 * N);
     constexpr bool ACCL = DG < 0;
     constexpr bool SK = DG == -2;    // all key blocks of a step staged together
+    constexpr bool WK = DG == -3;    // key fragments loaded from the global window array
     constexpr bool DALL = DG <= 0;   // a step's digits formed before its blocks run
-    constexpr bool DOUBLE = DALL && !SK;
+    constexpr bool DOUBLE = DALL && !SK && !WK;
     constexpr int NPASS = R / RP;
     static_assert(!ACCL || NPASS == 1, "LDS accumulator mode needs one row pass");
     // small N: accumulator component 1 in LDS as well (right after component 0)
@@ -428,9 +487,9 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
 
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     int8_t* dbuf = (int8_t*)smem;
-    size_t off = (size_t)(SK ? NB : ACCL ? l : DALL ? NB : DG) * R * 1024;
+    size_t off = (size_t)(SK || WK ? NB : ACCL ? l : DALL ? NB : DG) * R * 1024;
     uint8_t* kbuf = smem + off;
-    off += (size_t)(SK ? NB : DOUBLE ? 2 : 1) * KC * KCS;
+    off += (size_t)(SK ? NB : WK ? 0 : DOUBLE ? 2 : 1) * KC * KCS;
     T* acc0 = (T*)(smem + off);  // ACCL: accumulator component 0, [N/4][16 cts][4]
 
     // With all digits of a step formed before its blocks (DALL) the
@@ -626,7 +685,70 @@ __global__ __launch_bounds__(THREADS, 1) __attribute__((amdgpu_waves_per_eu(2, 2
             __syncthreads();
         }
     }
-    if constexpr (!SK) for (int i = 0; i < n; i++) {
+    // Windowed-key schedule (WK): the key blocks of a step run back to back
+    // (the key is read from the window array, not staged); four barriers per
+    // step: after component 0's digits, after parking component 1's rows,
+    // between the components' blocks and at the step end.
+    if constexpr (WK) {
+        v4i F0[4], F1[4];  // fragment ring of mfma_block_wk
+        constexpr size_t BLK = (size_t)2 * NL * 2 * N;  // windows per (u,p) block
+        const size_t vo = (size_t)v * NL * 2 * N + (size_t)((N - 1) - 16 * jr - (lane & 15) + 16 * (lane >> 4));
+        auto wbase = [&](int i, int ub) { return a.win + ((size_t)i * NB + ub) * BLK + vo; };
+        {
+            const uint4* b = wbase(0, 0);
+            F0[0] = __builtin_bit_cast(v4i, b[0]);
+            F0[1] = __builtin_bit_cast(v4i, b[64]);
+            F1[1] = __builtin_bit_cast(v4i, b[64 * (1 - 16)]);
+        }
+        for (int i = 0; i < n; i++) {
+            const int ab = cd_live ? (int)mod_switch<T>(a_next, LG) : 0;
+            if (i + 1 < n) a_next = lwe_cd[i + 1];
+            digits_phase<T, R, 1>(acc0, ab, dbuf, 0, 0, l, l, a.bg_bits);
+            __syncthreads();
+            if constexpr (PARK) if (v == 1) {
+                // this step's component-1 input rows (no fold has touched them yet)
+                uint32_t ro = (uint32_t)rbase0;
+                __asm__ volatile("" : "+v"(ro));
+#pragma unroll
+                for (int q = 0; q < RP; q++) {
+                    vec4 o;
+#pragma unroll
+                    for (int e = 0; e < 4; e++) o[e] = accr[q][e];
+                    *(vec4*)(acc0 + ro + q * STEP4) = o;
+                }
+            }
+            __syncthreads();
+            // component 1's digits are formed into their own l blocks while
+            // component 0's blocks run: the v = 0 waves before their blocks,
+            // the v = 1 waves after theirs (one of each per SIMD)
+            int8_t* dbuf1 = dbuf + (size_t)l * R * 1024;
+            const T* rows1 = PARK ? acc0 : acc1;
+            if (v == 0) digits_phase<T, R, 1, false, 2, false, THREADS / 2>(rows1, ab, dbuf1, 0, 0, l, l, a.bg_bits,
+                                                                            nullptr, 0);
+            for (int ub = 0; ub < NB; ub++) {
+                if (ub == l) {
+                    if (v == 1) digits_phase<T, R, 1, false, 2, false, THREADS / 2>(rows1, ab, dbuf1, 0, 0, l, l,
+                                                                                    a.bg_bits, nullptr, 1);
+                    __syncthreads();
+                }
+                const uint4* nxt = ub + 1 < NB ? wbase(i, ub + 1) : i + 1 < n ? wbase(i + 1, 0) : wbase(i, ub);
+                mfma_block_wk<T, R>(wbase(i, ub), nxt, dbuf + (size_t)ub * R * 1024, v, jr, accr, F0, F1);
+            }
+            uint32_t ro = (uint32_t)rbase;
+            __asm__ volatile("" : "+v"(ro));
+            if (rows_lds) {
+#pragma unroll
+                for (int q = 0; q < RP; q++) {
+                    vec4 o;
+#pragma unroll
+                    for (int e = 0; e < 4; e++) o[e] = accr[q][e];
+                    *(vec4*)(acc0 + ro + q * STEP4) = o;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if constexpr (!SK && !WK) for (int i = 0; i < n; i++) {
         const int ab = cd_live ? (int)mod_switch<T>(a_next, LG) : 0;
         if (i + 1 < n) a_next = lwe_cd[i + 1];
         if (DALL && !ACCL) {
@@ -998,6 +1120,7 @@ size_t lds_need(const tfhe_ctx* c, int dg) {
     const int NL = c->q == 32 ? 4 : 8;
     const size_t kslot = N <= 256 ? 4 * (2ull * NL * 2 * N + KCOPY_PAD) : 2ull * NL * 2 * N;
     if (dg == -2) return 2ull * l * (N / 64) * 1024 + 2ull * l * kslot + 2ull * N * CTS * word_bytes(c);
+    if (dg == -3) return 2ull * l * (N / 64) * 1024 + (size_t)N * CTS * word_bytes(c);
     size_t b = (size_t)(dg < 0 ? l : dg == 0 ? 2 * l : dg) * (N / 64) * 1024;
     b += (dg <= 0 ? 2 : 1) * kslot;
     if (dg < 0) b += (size_t)N * CTS * word_bytes(c) * (2ull * N * CTS * word_bytes(c) <= 65536 ? 2 : 1);
@@ -1039,6 +1162,7 @@ int plan_dg(const tfhe_ctx* c, int R, int rp, uint32_t B) {
                                ? (size_t)c->prop.maxSharedMemoryPerMultiProcessor
                                : (size_t)160 * 1024;
     const bool both_lds = 2ull * c->p.N * CTS * word_bytes(c) <= 65536;
+    if (rp == R && c->digit_blocks == 0 && c->d_win && lds_need(c, -3) <= max_lds) return -3;
     if (rp == R && c->digit_blocks == 0 && both_lds && c->p.l <= 4 && lds_need(c, -2) <= max_lds) {
         // The step-keyed schedule stages a whole step's keys, which can leave
         // room for fewer workgroups per CU than the per-component one (at
@@ -1063,6 +1187,9 @@ int dispatch_dg(tfhe_ctx* c, const BrArgs& a, int dg, hipStream_t s) {
     }
     if constexpr (RP == R && 2 * R * 64 * CTS * sizeof(T) <= 65536) {
         if (dg == -2) return launch_t<T, R, RP, -2>(c, a, lds_need(c, -2), s);
+    }
+    if constexpr (sizeof(T) == 4 && R == 16 && RP == 16) {
+        if (dg == -3) return launch_t<T, R, RP, -3>(c, a, lds_need(c, -3), s);
     }
     if (dg == 0) return launch_t<T, R, RP, 0>(c, a, lds_need(c, 0), s);
     if (dg == 2) return launch_t<T, R, RP, 2>(c, a, lds_need(c, 2), s);
@@ -1213,6 +1340,7 @@ int launch_br_mfma(tfhe_ctx* c, const void* lwe_in, const void* tv, const int32_
     BrArgs a;
     a.lwe = lwe_in;
     a.bsk8 = c->d_bsk8;
+    a.win = (const uint4*)c->d_win;
     a.tv = tv;
     a.tv_index = tv_index;
     a.out = big_out;

@@ -165,6 +165,24 @@ __global__ void bsk_limbs_kernel(const T* bsk, int8_t* bsk8, size_t polys, int N
     }
 }
 
+// win[row][x] = bytes x .. x+15 of limb row `row` of bsk8 (zero past its
+// 2N bytes): the 16-byte-aligned A fragments of the windowed-key blind
+// rotation, one per byte offset.
+__global__ void key_windows_kernel(const int8_t* bsk8, uint4* win, size_t rows, int N2) {
+    const size_t total = rows * N2;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t row = idx / N2;
+        const int x = (int)(idx % N2);
+        const uint8_t* S = (const uint8_t*)bsk8 + row * N2;
+        uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+            if (x + j < N2) w[j >> 2] |= (uint32_t)S[x + j] << (8 * (j & 3));
+        win[idx] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
 template <typename T>
 __global__ void fill_kernel(T* dst, size_t count, T value) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
@@ -222,6 +240,22 @@ extern "C" int tfhe_ctx_create(const tfhe_params* p, const void* bsk, size_t bsk
         return rc;
     }
     if ((rc = launch_bsk_limbs(c, 0))) { tfhe_ctx_destroy(c); return rc; }
+    if (c->q == 32 && p->N == 1024) {
+        // the windowed-key blind rotation's fragments (16 bytes per byte of
+        // bsk8: 968 MB at n = 630, l = 3); without room for them the kernel
+        // stages the key in LDS instead
+        const size_t rows = polys * NL;
+        c->win_bytes = rows * 2 * p->N * 16;
+        if (hipMalloc(&c->d_win, c->win_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            c->d_win = nullptr;
+            c->win_bytes = 0;
+        } else {
+            hipLaunchKernelGGL(key_windows_kernel, dim3(4096), dim3(256), 0, 0, (const int8_t*)c->d_bsk8,
+                               (uint4*)c->d_win, rows, 2 * (int)p->N);
+            if ((rc = hip_check(c, hipGetLastError(), "launch key_windows"))) { tfhe_ctx_destroy(c); return rc; }
+        }
+    }
     if (c->q == 32)
         hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(8), dim3(256), 0, 0, (uint32_t*)c->d_gate_tv, (size_t)p->N,
                            (uint32_t)1u << 29);
@@ -255,6 +289,7 @@ extern "C" void tfhe_ctx_destroy(tfhe_ctx* c) {
     if (c->ws_event) hipEventDestroy(c->ws_event);
     if (c->d_bsk) hipFree(c->d_bsk);
     if (c->d_bsk8) hipFree(c->d_bsk8);
+    if (c->d_win) hipFree(c->d_win);
     if (c->d_ksk) hipFree(c->d_ksk);
     if (c->d_gate_tv) hipFree(c->d_gate_tv);
     if (c->d_false) hipFree(c->d_false);

@@ -99,6 +99,8 @@ struct tfhe_ctx {
     void* d_radix_tv = nullptr;  // radix look-up test polynomials [8][N] words
     void* d_bsk = nullptr;     // [n][(k+1)l][k+1][N] words
     int8_t* d_bsk8 = nullptr;  // [n][(k+1)l][k+1][LIMBS][2N] Toeplitz limb form
+    void* d_win = nullptr;     // [n][(k+1)l][k+1][LIMBS][2N] 16-byte windows of bsk8 (N = 1024, q = 32), or null
+    size_t win_bytes = 0;
     void* d_ksk = nullptr;     // [kN][t][2^b][ks_row] words (rows padded to whole 128-byte lines)
     size_t ks_row = 0;         // words per KSK row on the device: n+1 rounded up to 128 bytes
     void* d_gate_tv = nullptr; // N words of 1/8
