@@ -76,6 +76,39 @@ def test_std_bootstrap_batch_4096(std):
         assert np.array_equal(gk[i], oracle.keyswitch(P, K.ksk, g[i])), i
 
 
+@pytest.mark.parametrize("dbk", [4, 1, 3])
+def test_std_key_schedules(std, dbk):
+    """The schedules that stage the key in LDS -- one component's blocks with
+    component 0 of the accumulator in LDS (digit_blocks 4, also what a context
+    without room for the key windows runs), one block at a time (1), all of a
+    step's blocks with the accumulator in global memory (3) -- give the
+    windowed-key default's bits on a ragged batch of two groups (with the
+    multi-workgroup path for small batches switched off), and the oracle's on
+    sampled outputs."""
+    K, ctx = std
+    B = 19
+    lwe = si.torus(73, 90 + dbk, B * (P.n + 1), P.q).reshape(B, P.n + 1)
+    d_lwe = to_dev(P, lwe)
+    outs = []
+    try:
+        for tune in (0, dbk):
+            say("std bootstrap, digit_blocks", tune)
+            # split_groups=0: the one-workgroup-per-group kernel these schedules belong to
+            ctx.set_tuning(digit_blocks=tune, split_groups=0)
+            out = empty(P, B, P.N + 1)
+            ctx.tfhe_bootstrap_batch(d_lwe, out)
+            torch.cuda.synchronize()
+            outs.append(from_dev(P, out))
+    finally:
+        ctx.set_tuning(digit_blocks=0, split_groups=-1)
+    assert np.array_equal(outs[0], outs[1])
+    tv = oracle.gate_testv(P)
+    idx = [0, 18]
+    want = oracle.parallel_map(lambda i: oracle.bootstrap(P, K.bsk, lwe[i], tv), idx)
+    for i, w_ in zip(idx, want):
+        assert np.array_equal(outs[1][i], w_), (dbk, i)
+
+
 def test_std_edge_inputs(std):
     """The boundary inputs of the toy edge test at the standard parameters
     (lg = 11, key-switch rounding to 16 bits): every output word of the
