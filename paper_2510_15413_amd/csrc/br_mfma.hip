@@ -21,15 +21,19 @@
 // fragment is loaded per diagonal and reused by every (a, c) on it.
 // The key limbs of step i are stored (once per context) as reversed extended
 // byte arrays S[x] = limb(Kext[N-1-x]); a lane's 16 A bytes are contiguous
-// in S (unaligned by a per-lane constant, fixed with v_alignbyte, or for
-// N <= 256 read from one of four byte-shifted copies staged in LDS).
+// in S, unaligned by a per-lane constant.  At N = 1024 (32-bit words) the
+// context also holds the 16 bytes at every offset of S in an aligned slot
+// (the key windows) and each fragment is one 16-byte global load; otherwise
+// the key is staged in LDS and a fragment is 5 words fixed with v_alignbyte,
+// or for N <= 256 4 aligned words of one of four byte-shifted copies.
 // Accumulators are laid out [v][N/4][16 cts][4 coefs].  With one row pass
 // every wave keeps its rows in registers across the n steps and stores them
 // at each step's end for the next rotate-diff: component 0 to LDS, component
-// 1 to LDS too when both fit in 64 KB (small N), else to a per-workgroup
-// global buffer (L2 resident).  With several passes both components live in
-// a global ping-pong buffer, and the first pass of a step caches its digits
-// in global memory for the others.  Digits and key limbs are staged in LDS.
+// 1 to LDS too when both fit in 64 KB (small N), else parked in component
+// 0's region during the step and in a per-workgroup global buffer at the
+// end.  With several passes both components live in a global ping-pong
+// buffer, and the first pass of a step caches its digits in global memory
+// for the others.  Digits are formed into LDS.
 #include <algorithm>
 
 #include "fhesql_internal.h"
