@@ -103,8 +103,11 @@ size_t tfhe_ksk_words(const tfhe_params* p);
  * has room, the BSK's 16-byte key windows (16 bytes per byte of the limb
  * form: 968 MB at n = 630, l = 3), from which the blind rotation reads its
  * A fragments directly; without room it stages the key in LDS instead (same
- * output bits).  Blocks until the keys are on the device.  The context owns
- * its copies; the caller keeps ownership of bsk/ksk. */
+ * output bits).  With torus_bits = 32 it also keeps the key-switching table
+ * as int8 limbs (4 bytes per word, 84 MB at the standard set) for the MFMA
+ * key switch; without room the key switch reads the word table.  Blocks
+ * until the keys are on the device.  The context owns its copies; the
+ * caller keeps ownership of bsk/ksk. */
 int tfhe_ctx_create(const tfhe_params* p, const void* bsk, size_t bsk_bytes,
                     const void* ksk, size_t ksk_bytes, int keys_on_device,
                     tfhe_ctx** out);

@@ -183,6 +183,27 @@ __global__ void key_windows_kernel(const int8_t* bsk8, uint4* win, size_t rows, 
     }
 }
 
+// ksk8[m][w][k] = limb m of KSK row k, word w (zero for w > n): the
+// balanced int8 limbs (sum_m limb_m 2^{8m} = word mod 2^32) of the 32-bit
+// key-switching table, each word's K = kN*t*2^b limbs contiguous, for the
+// MFMA key switch.
+__global__ void ksk_limbs_kernel(const uint32_t* ksk, int8_t* ksk8, size_t ks_row, int n, int Wp, size_t K) {
+    const size_t total = (size_t)Wp * K;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int w = (int)(idx / K);
+        const size_t k = idx % K;
+        const uint32_t val = w <= n ? ksk[k * ks_row + w] : 0u;
+        int carry = 0;
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            int r = (int)((val >> (8 * m)) & 0xFF) + carry;
+            carry = r >= 128;
+            ksk8[(size_t)m * total + idx] = (int8_t)(r - (carry << 8));
+        }
+    }
+}
+
 template <typename T>
 __global__ void fill_kernel(T* dst, size_t count, T value) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
@@ -240,6 +261,21 @@ extern "C" int tfhe_ctx_create(const tfhe_params* p, const void* bsk, size_t bsk
         return rc;
     }
     if ((rc = launch_bsk_limbs(c, 0))) { tfhe_ctx_destroy(c); return rc; }
+    if (c->q == 32) {
+        // the MFMA key switch's limb table (4 bytes per word: 84 MB at the
+        // standard set); without room the key switch reads the word table
+        c->ks_wp = (int)((p->n + 1 + 15) / 16 * 16);
+        const size_t K = ks_rows;
+        if (hipMalloc((void**)&c->d_ksk8, 4 * (size_t)c->ks_wp * K) != hipSuccess) {
+            (void)hipGetLastError();
+            c->d_ksk8 = nullptr;
+        } else {
+            c->ksk8_bytes = 4 * (size_t)c->ks_wp * K;
+            hipLaunchKernelGGL(ksk_limbs_kernel, dim3(4096), dim3(256), 0, 0, (const uint32_t*)c->d_ksk, c->d_ksk8,
+                               c->ks_row, (int)p->n, c->ks_wp, K);
+            if ((rc = hip_check(c, hipGetLastError(), "launch ksk_limbs"))) { tfhe_ctx_destroy(c); return rc; }
+        }
+    }
     if (c->q == 32 && p->N == 1024) {
         // the windowed-key blind rotation's fragments (16 bytes per byte of
         // bsk8: 968 MB at n = 630, l = 3); without room for them the kernel
@@ -291,6 +327,7 @@ extern "C" void tfhe_ctx_destroy(tfhe_ctx* c) {
     if (c->d_bsk8) hipFree(c->d_bsk8);
     if (c->d_win) hipFree(c->d_win);
     if (c->d_ksk) hipFree(c->d_ksk);
+    if (c->d_ksk8) hipFree(c->d_ksk8);
     if (c->d_gate_tv) hipFree(c->d_gate_tv);
     if (c->d_false) hipFree(c->d_false);
     if (c->d_radix_tv) hipFree(c->d_radix_tv);

@@ -103,6 +103,9 @@ struct tfhe_ctx {
     size_t win_bytes = 0;
     void* d_ksk = nullptr;     // [kN][t][2^b][ks_row] words (rows padded to whole 128-byte lines)
     size_t ks_row = 0;         // words per KSK row on the device: n+1 rounded up to 128 bytes
+    int8_t* d_ksk8 = nullptr;  // q = 32: [4 limbs][ks_wp][kN*t*2^b] balanced int8 limbs of the KSK, row-transposed
+    int ks_wp = 0;             // n+1 rounded up to 16 (rows of d_ksk8 past n are zero)
+    size_t ksk8_bytes = 0;
     void* d_gate_tv = nullptr; // N words of 1/8
     void* d_false = nullptr;   // trivial FALSE ciphertext (0^n, -1/8)
     // workspace (grown on demand), shared by the calls on this context.  A

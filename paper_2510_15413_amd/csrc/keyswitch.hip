@@ -200,6 +200,183 @@ __global__ __launch_bounds__(THREADS) void keyswitch_kernel(const T* __restrict_
         if (w0 + k <= n) dst[w0 + k] = acc[k];
 }
 
+// ---- 32-bit words: the key switch as int8 matrix products.
+//
+// out[c][w] = [w == n] b'_c - sum_k X[c][k] Y[k][w]  (mod 2^32), with X the
+// one-hot digit matrix, X[c][(i*t + j)*V + v] = [digit_ij(c) == v], and Y the
+// table rows.  Y is split into balanced int8 limbs, Y = sum_m 2^{8m} Y_m; each
+// limb product is exact in int32 (kN*t ones per row of X, |limb| <= 128), and
+// the limb sums are combined mod 2^32 at the end.  v_mfma_i32_16x16x64_i8
+// takes A = a 16-word tile of Y_m (each word's 64 k of a chunk contiguous,
+// staged in LDS chunk by chunk, double-buffered) and B = 16 ciphertexts'
+// one-hot rows of the chunk, formed in registers from the digits (a lane's 16
+// bytes are PPL = 16/V consecutive (i, j) pairs, one byte set per pair).  A
+// workgroup of 4 waves owns TW word tiles (one: two would hold 268 registers
+// per lane, one wave per SIMD) and 64 KM_CT ciphertexts (KM_CT tiles of 16
+// per wave: 4, or 2 when the grid would not fill the CUs), so each staged A
+// fragment feeds KM_CT MFMAs; a wave's output tile holds 4 consecutive words
+// of one ciphertext per lane.
+
+template <int V, typename D, int TW, int KM_CT>
+__global__ __launch_bounds__(THREADS) void ks_mfma_kernel(const uint32_t* __restrict__ big, const D* __restrict__ dig,
+                                                          const int8_t* __restrict__ ytab, uint32_t* out,
+                                                          const uint64_t* out_ptrs, int B, int n, int kN, int t,
+                                                          int bb, int Wp, KsPlace pl) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    constexpr int PPL = 16 / V;                 // (i, j) pairs in a lane's 16 bytes of a chunk
+    constexpr int CHU = TW * 4 * 16 * 4;        // 16-byte units of table per chunk: TW tiles x 4 limbs x 16 words x 64 k
+    constexpr int UPT = CHU / THREADS;          // units per thread
+    static_assert(CHU % THREADS == 0, "whole units per thread");
+    __shared__ __attribute__((aligned(16))) int8_t tb[2][CHU * 16];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int z = (int)(blockIdx.x % 8) * pl.per + (int)(blockIdx.x / 8);
+    if (z >= pl.tiles * pl.groups) return;  // padding of the last run
+    const int tile = pl.tile_major ? z / pl.groups : z % pl.tiles;
+    const int grp = pl.tile_major ? z % pl.groups : z / pl.tiles;
+    const int w0 = tile * TW * 16;
+    const size_t K = (size_t)kN * t * V;
+    const int NCH = (int)(K / 64);
+    const size_t plane = (size_t)Wp * K;  // bytes of one limb plane
+    const int g = lane >> 4;
+    const int cl = grp * 64 * KM_CT + wave * 16 * KM_CT + (lane & 15);  // this lane's ciphertext of tile 0 (tile ct: + 16 ct)
+
+    // table staging: unit u = tid + q*THREADS is row R = u/4 (limb m = R / (16 TW), word
+    // w0 + R % (16 TW)), 16 bytes `part` = u % 4 of the chunk's 64
+    const int8_t* src[UPT];
+    int dst[UPT];
+#pragma unroll
+    for (int q = 0; q < UPT; q++) {
+        const int u = tid + q * THREADS, R = u >> 2, part = u & 3;
+        const int m = R / (16 * TW), w = w0 + R % (16 * TW);
+        src[q] = w < Wp ? ytab + (size_t)m * plane + (size_t)w * K + 16 * part : nullptr;
+        dst[q] = R * 64 + 16 * part;
+    }
+    uint4 st[UPT];
+    auto fetch = [&](int ch) {
+#pragma unroll
+        for (int q = 0; q < UPT; q++) st[q] = src[q] ? *(const uint4*)(src[q] + (size_t)ch * 64) : make_uint4(0, 0, 0, 0);
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < UPT; q++) *(uint4*)(tb[buf] + dst[q]) = st[q];
+    };
+
+    // digits of a lane's pairs in chunk ch for ciphertext tile ct: the pairs
+    // P0 .. P0+PPL-1 (P0 = (64 ch + 16 g) / V) touch rows i0 and i0 + 1
+    auto digit_rows = [&](int ch, int ct, uint32_t& lo, uint32_t& hi, int& j0) {
+        const int P0 = (64 * ch + 16 * g) / V;
+        const int i0 = P0 / t;
+        j0 = P0 - i0 * t;
+        const int c = cl + 16 * ct;
+        const bool live = c < B;
+        lo = live ? (uint32_t)dig[(size_t)i0 * B + c] : 0u;
+        hi = live && i0 + 1 < kN ? (uint32_t)dig[(size_t)(i0 + 1) * B + c] : 0u;
+    };
+    auto onehot = [&](uint32_t lo, uint32_t hi, int j0) -> v4i {
+        uint32_t wv[4] = {0, 0, 0, 0};
+        int j = j0;
+        bool up = false;
+#pragma unroll
+        for (int p = 0; p < PPL; p++) {
+            const uint32_t r = up ? hi : lo;
+            const int d = (int)((r >> ((t - 1 - j) * bb)) & (V - 1));
+            const int pos = p * V + d;  // byte of the lane's 16
+#pragma unroll
+            for (int e = 0; e < 4; e++) wv[e] |= (pos >> 2) == e ? 1u << (8 * (pos & 3)) : 0u;
+            if (++j == t) { j = 0; up = true; }
+        }
+        return v4i{(int)wv[0], (int)wv[1], (int)wv[2], (int)wv[3]};
+    };
+
+    v4i acc[TW][KM_CT][4];
+#pragma unroll
+    for (int wt = 0; wt < TW; wt++)
+#pragma unroll
+        for (int ct = 0; ct < KM_CT; ct++)
+#pragma unroll
+            for (int m = 0; m < 4; m++) acc[wt][ct][m] = v4i{0, 0, 0, 0};
+
+    fetch(0);
+    stage(0);
+    uint32_t dlo[KM_CT], dhi[KM_CT];
+    int dj0 = 0;
+#pragma unroll
+    for (int ct = 0; ct < KM_CT; ct++) digit_rows(0, ct, dlo[ct], dhi[ct], dj0);
+    __syncthreads();
+    for (int ch = 0; ch < NCH; ch++) {
+        const int buf = ch & 1;
+        if (ch + 1 < NCH) fetch(ch + 1);
+        v4i bx[KM_CT];
+#pragma unroll
+        for (int ct = 0; ct < KM_CT; ct++) bx[ct] = onehot(dlo[ct], dhi[ct], dj0);
+        if (ch + 1 < NCH) {
+#pragma unroll
+            for (int ct = 0; ct < KM_CT; ct++) digit_rows(ch + 1, ct, dlo[ct], dhi[ct], dj0);
+        }
+#pragma unroll
+        for (int wt = 0; wt < TW; wt++)
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                const v4i a = *(const v4i*)(tb[buf] + ((m * TW + wt) * 16 + (lane & 15)) * 64 + 16 * g);
+#pragma unroll
+                for (int ct = 0; ct < KM_CT; ct++)
+                    acc[wt][ct][m] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bx[ct], acc[wt][ct][m], 0, 0, 0);
+            }
+        if (ch + 1 < NCH) stage(buf ^ 1);
+        __syncthreads();
+    }
+    // lane holds words w0 + 16 wt + 4g + e of ciphertext cl + 16 ct
+#pragma unroll
+    for (int ct = 0; ct < KM_CT; ct++) {
+        const int c = cl + 16 * ct;
+        if (c >= B) continue;
+        uint32_t* dstp = out_ptrs ? (uint32_t*)(uintptr_t)out_ptrs[c] : out + (size_t)c * (n + 1);
+        const uint32_t body = big[(size_t)c * (kN + 1) + kN];
+#pragma unroll
+        for (int wt = 0; wt < TW; wt++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int w = w0 + 16 * wt + 4 * g + e;
+                if (w > n) continue;
+                uint32_t val = 0;
+#pragma unroll
+                for (int m = 0; m < 4; m++) val += (uint32_t)acc[wt][ct][m][e] << (8 * m);
+                dstp[w] = (w == n ? body : 0u) - val;
+            }
+    }
+}
+
+template <int V, typename D, int TW, int KM_CT>
+int launch_mfma_ct(tfhe_ctx* c, const uint32_t* big, const D* dig, uint32_t* out, const uint64_t* out_ptrs,
+                   uint32_t B, hipStream_t s) {
+    const int n = (int)c->p.n, kN = (int)(c->p.k * c->p.N), t = (int)c->p.ks_t, bb = (int)c->p.ks_base_bits;
+    KsPlace pl;
+    pl.tiles = (c->ks_wp / 16 + TW - 1) / TW;
+    pl.groups = (int)((B + 64 * KM_CT - 1) / (64 * KM_CT));
+    pl.per = (pl.tiles * pl.groups + 7) / 8;
+    const double table = 4.0 * c->ks_wp * kN * t * V, inputs = (double)B * kN * sizeof(D);
+    pl.tile_major = table > inputs ? 1 : 0;
+    hipLaunchKernelGGL((ks_mfma_kernel<V, D, TW, KM_CT>), dim3(8 * pl.per), dim3(THREADS), 0, s, big, dig,
+                       (const int8_t*)c->d_ksk8, out, out_ptrs, (int)B, n, kN, t, bb, c->ks_wp, pl);
+    return hip_check(c, hipGetLastError(), "launch ks_mfma");
+}
+
+template <int V, typename D, int TW>
+int launch_mfma_ks(tfhe_ctx* c, const uint32_t* big, void* dig_ws, uint32_t* out, const uint64_t* out_ptrs,
+                   uint32_t B, hipStream_t s) {
+    const int kN = (int)(c->p.k * c->p.N), t = (int)c->p.ks_t, bb = (int)c->p.ks_base_bits;
+    D* dig = (D*)dig_ws;
+    hipLaunchKernelGGL((ks_digits_kernel<uint32_t, D>), dim3((kN + 63) / 64, (B + 63) / 64), dim3(THREADS), 0, s,
+                       big, dig, (int)B, kN, t * bb);
+    // 4 ciphertext tiles per wave, or 2 when that leaves CUs idle (measured:
+    // 4096 ciphertexts at n = 64 0.069 -> 0.052 ms; 4 is faster once the grid
+    // fills the chip)
+    const int cus = c->prop.multiProcessorCount > 0 ? c->prop.multiProcessorCount : 256;
+    const int64_t wgs4 = (int64_t)((c->ks_wp / 16 + TW - 1) / TW) * ((B + 255) / 256);
+    if (wgs4 < cus) return launch_mfma_ct<V, D, TW, 2>(c, big, dig, out, out_ptrs, B, s);
+    return launch_mfma_ct<V, D, TW, 4>(c, big, dig, out, out_ptrs, B, s);
+}
+
 template <typename T, typename D, int V, int WPW, int P>
 int launch_p(tfhe_ctx* c, const T* big, void* dig_ws, T* out, const uint64_t* out_ptrs, uint32_t B, hipStream_t s) {
     const int n = (int)c->p.n, kN = (int)(c->p.k * c->p.N), t = (int)c->p.ks_t, bb = (int)c->p.ks_base_bits;
@@ -245,6 +422,15 @@ int launch_v(tfhe_ctx* c, const T* big, void* dig, T* out, const uint64_t* out_p
 template <typename T, int V>
 int launch_w(tfhe_ctx* c, const void* big, void* dig, void* out, const uint64_t* out_ptrs, uint32_t B,
              hipStream_t s) {
+    if constexpr (sizeof(T) == 4) {
+        // the MFMA form: a lane's pairs of a chunk must span at most two rows i
+        if (c->d_ksk8 && 16 / V <= (int)c->p.ks_t) {
+            const uint32_t* b32 = (const uint32_t*)big;
+            uint32_t* o32 = (uint32_t*)out;
+            if (c->p.ks_t * c->p.ks_base_bits <= 16) return launch_mfma_ks<V, uint16_t, 1>(c, b32, dig, o32, out_ptrs, B, s);
+            return launch_mfma_ks<V, uint32_t, 1>(c, b32, dig, o32, out_ptrs, B, s);
+        }
+    }
     if (c->p.ks_t * c->p.ks_base_bits <= 16)
         return launch_v<T, uint16_t, V, 16>(c, (const T*)big, dig, (T*)out, out_ptrs, B, s);
     return launch_v<T, uint32_t, V, 16>(c, (const T*)big, dig, (T*)out, out_ptrs, B, s);

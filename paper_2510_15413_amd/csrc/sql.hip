@@ -430,7 +430,7 @@ extern "C" int sql_server_create(tfhe_ctx* c, size_t budget, uint32_t max_batch,
     const size_t wb = word_bytes(c), lw = c->p.n + 1, bw = (size_t)c->p.k * c->p.N + 1;
     const size_t NL = c->q == 32 ? 4 : 8;
     const size_t keys = (tfhe_bsk_words(&c->p) + tfhe_ksk_words(&c->p)) * wb +
-                        (size_t)c->p.n * 2 * c->p.l * 2 * NL * 2 * c->p.N + c->win_bytes;
+                        (size_t)c->p.n * 2 * c->p.l * 2 * NL * 2 * c->p.N + c->win_bytes + c->ksk8_bytes;
     const size_t lwe_b = al256((size_t)max_batch * lw * wb), big_b = al256((size_t)max_batch * bw * wb);
     const size_t ptr_b = al256((size_t)max_batch * 8), tvi_b = al256((size_t)max_batch * 4);
     // blind-rotation workspace, reused by the key switch's digits
