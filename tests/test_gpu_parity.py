@@ -538,13 +538,15 @@ def test_bootstrap_every_ring_size(q, N, passes):
     ctx.close()
 
 
-@pytest.mark.parametrize("q,ks_bits,ks_t", [(32, 3, 8), (32, 4, 8), (64, 4, 8), (32, 2, 4), (32, 1, 8)])
+@pytest.mark.parametrize("q,ks_bits,ks_t", [(32, 3, 8), (32, 4, 8), (64, 4, 8), (32, 2, 4), (32, 1, 8), (32, 1, 4)])
 def test_keyswitch_staging_variants(q, ks_bits, ks_t):
-    """Key switching with other key-switching bases, where another number of
-    input coefficients fits one staging round (32-bit: 2 coefficients per
-    barrier at base 2^3 x 8 levels, 1 at base 2^4 x 8, 8 at bases 2^2 x 4 and
-    2^1 x 8), with an LWE of 41 words (a ragged word tile) and 300
-    ciphertexts (a ragged ciphertext group): the oracle's bits."""
+    """Key switching with other key-switching bases, with an LWE of 41 words
+    (a ragged word tile) and 300 ciphertexts (a ragged ciphertext group): the
+    oracle's bits.  With 32-bit words the int8 MFMA form runs for every base
+    whose one-hot bytes of a lane (16/2^b (i, j) pairs) span at most two
+    table rows, i.e. 16/2^b <= t -- bases 2^3, 2^4, 2^2 x 4 and 2^1 x 8 --
+    and the LDS gather kernel for 2^1 x 4 (8 pairs over 4 levels); with
+    64-bit words the gather kernel (one staged coefficient per barrier)."""
     p = si.Params(f"ks{q}_{ks_bits}_{ks_t}", q, 40, 1, 256, 8 if q == 32 else 6, 2 if q == 32 else 4,
                   ks_bits, ks_t, 20, 25 if q == 32 else 51)
     K = oracle.Keys(p, si.KEY_SEED_BASE + 70 + ks_bits + q)
